@@ -1,0 +1,240 @@
+/*
+ * Reference oracle: a plain, slow FP64 implementation of the bond-based
+ * peridynamic beam solve.  TEST INFRASTRUCTURE ONLY: it is used by the test
+ * suite, the smoke check and the CPU baseline of the benchmark, and never by
+ * the product library.  It shares no code with the GPU path.
+ *
+ * What it computes (one sample):
+ *   - bond stretch s = (|xi + eta| - |xi|) / |xi|           (section 2.1, Eq. PD_Force_Function)
+ *   - bond force f = c_b (1 - d_b) s along the deformed bond  (appendix A, Eq. exp_scalar_force)
+ *   - irreversible damage d_b = D(kappa_b), kappa_b the largest stretch seen so
+ *     far; D is the appendix-A softening law (Eq. exp_damage_parameter) or the
+ *     piecewise-linear envelope with the same fracture energy
+ *   - nodal force density L_i = sum_j f e_ij V_j              (section 2.1, Eq. PD_EOM_Dynamic)
+ *   - damped velocity-Verlet under prescribed support / load displacements
+ *   - support reaction R^n and its running maximum Q, the peak load (section 4, QoI)
+ *
+ * Every loop runs over the unique bond list in its given order; no fusion,
+ * no reordering, no compensation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PDO_PI 3.14159265358979323846
+#define PDO_LAW_EXPLIN 0
+#define PDO_LAW_TRILINEAR 1
+
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_bonds;
+    const int32_t *bond_i;     /* [n_bonds], bond_i < bond_j */
+    const int32_t *bond_j;     /* [n_bonds] */
+    const double *xi;          /* [n_bonds][3] reference bond vector x_j - x_i */
+    const double *s0_node;     /* [n_nodes] linear-elastic limit stretch */
+    const double *c_node;      /* [n_nodes] micromodulus */
+    int64_t n_support;
+    const int32_t *support;    /* nodes with u_z = 0 */
+    int64_t n_load;
+    const int32_t *load;       /* nodes with u_z = -(n+1) du */
+    double volume;             /* nodal volume dx^3 */
+    double rho;                /* mass density */
+    double damping;            /* viscous damping coefficient (force density per velocity) */
+    double dt;
+    double du;                 /* load displacement increment per step */
+    int64_t n_steps;
+    int32_t law;               /* PDO_LAW_* */
+    double k, alpha;           /* softening shape parameters */
+    double GF;                 /* fracture energy */
+    double delta;              /* horizon */
+    double load_offset;        /* load pad u_z = load_offset - (n+1) du (0 for a fresh run) */
+} pdo_problem;
+
+/* ---------------------------------------------------------------- material */
+
+/* Critical stretch s_c.
+ * EXPLIN: solve the 3D fracture-energy relation of appendix A
+ *   G_F = pi c s0 delta^5 (s0 - sc) P / (10 k (e^k - 1)(1 + alpha)),
+ *   P = 2k - 2e^k + alpha k - alpha k e^k + 2,
+ * for sc.  (The printed rearrangement, Eq. exp_sc, drops the (1 + alpha)
+ * factor inside the bracket; solving the energy relation itself is used.)
+ * TRILINEAR: envelope through (s0, c s0), (s1, 0.2 c s0), (sc, 0) with
+ * s1 = s0 + 0.2 (sc - s0); its softening area is 0.2 c s0 (sc - s0), and the
+ * same fracture-energy integral G_F = (pi delta^5 / 5) * area gives sc. */
+double pdo_critical_stretch(int32_t law, double s0, double c, double GF, double delta,
+                            double k, double alpha)
+{
+    double d5 = pow(delta, 5.0);
+    if (law == PDO_LAW_EXPLIN) {
+        double ek = exp(k);
+        double P = 2.0 * k - 2.0 * ek + alpha * k - alpha * k * ek + 2.0;
+        double s0_minus_sc = GF * 10.0 * k * (ek - 1.0) * (1.0 + alpha) / (PDO_PI * c * s0 * d5 * P);
+        return s0 - s0_minus_sc;
+    }
+    /* trilinear: GF = (pi d5 / 5) * 0.2 c s0 (sc - s0) */
+    return s0 + GF * 5.0 / (PDO_PI * d5 * 0.2 * c * s0);
+}
+
+/* Damage d = D(kappa) for a bond with limit stretch s0 and critical stretch sc
+ * (appendix A, Eq. exp_damage_parameter, clamped outside [s0, sc]). */
+double pdo_damage(int32_t law, double kappa, double s0, double sc, double k, double alpha)
+{
+    if (!(kappa > s0)) return 0.0;
+    if (kappa >= sc) return 1.0;
+    if (law == PDO_LAW_EXPLIN) {
+        double t = (kappa - s0) / (sc - s0);
+        double bracket = 1.0 - (1.0 - exp(-k * t)) / (1.0 - exp(-k)) + alpha * (1.0 - t);
+        return 1.0 - (s0 / kappa) * bracket / (1.0 + alpha);
+    }
+    /* trilinear envelope force / (c kappa) */
+    double s1 = s0 + 0.2 * (sc - s0);
+    double fenv;  /* envelope force divided by c */
+    if (kappa <= s1)
+        fenv = s0 * (1.0 - 0.8 * (kappa - s0) / (s1 - s0));
+    else
+        fenv = 0.2 * s0 * (sc - kappa) / (sc - s1);
+    return 1.0 - fenv / kappa;
+}
+
+/* ---------------------------------------------------------------- force */
+
+/* One force evaluation: L = sum over bonds of f e V, damage history updated in
+ * place.  kappa[b] holds the largest stretch bond b has seen (-inf initially). */
+static void force_eval(const pdo_problem *p, const double *u, double *kappa,
+                       const double *c_b, const double *s0_b, const double *sc_b,
+                       double *L)
+{
+    memset(L, 0, sizeof(double) * 3 * p->n_nodes);
+    for (int64_t b = 0; b < p->n_bonds; ++b) {
+        int32_t i = p->bond_i[b], j = p->bond_j[b];
+        const double *xi = p->xi + 3 * b;
+        double y[3];
+        for (int d = 0; d < 3; ++d) y[d] = xi[d] + (u[3 * j + d] - u[3 * i + d]);
+        double ylen = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+        double xlen = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+        double s = (ylen - xlen) / xlen;
+        if (s > kappa[b]) kappa[b] = s;
+        double dmg = pdo_damage(p->law, kappa[b], s0_b[b], sc_b[b], p->k, p->alpha);
+        double f = c_b[b] * (1.0 - dmg) * s;
+        for (int d = 0; d < 3; ++d) {
+            double fd = f * (y[d] / ylen) * p->volume;
+            L[3 * i + d] += fd;
+            L[3 * j + d] -= fd;
+        }
+    }
+}
+
+static void bond_params(const pdo_problem *p, double *c_b, double *s0_b, double *sc_b)
+{
+    for (int64_t b = 0; b < p->n_bonds; ++b) {
+        int32_t i = p->bond_i[b], j = p->bond_j[b];
+        c_b[b] = 0.5 * (p->c_node[i] + p->c_node[j]);
+        s0_b[b] = 0.5 * (p->s0_node[i] + p->s0_node[j]);
+        sc_b[b] = pdo_critical_stretch(p->law, s0_b[b], c_b[b], p->GF, p->delta, p->k, p->alpha);
+    }
+}
+
+/* Force on a frozen displacement field, with an optional damage history
+ * (kappa may be NULL for an undamaged body; otherwise it is updated). */
+int pdo_force(const pdo_problem *p, const double *u, double *kappa, double *L)
+{
+    int64_t nb = p->n_bonds;
+    double *c_b = malloc(sizeof(double) * nb), *s0_b = malloc(sizeof(double) * nb),
+           *sc_b = malloc(sizeof(double) * nb), *kap = NULL;
+    if (!c_b || !s0_b || !sc_b) return -2;
+    bond_params(p, c_b, s0_b, sc_b);
+    if (!kappa) {
+        kap = malloc(sizeof(double) * nb);
+        for (int64_t b = 0; b < nb; ++b) kap[b] = -INFINITY;
+    }
+    force_eval(p, u, kappa ? kappa : kap, c_b, s0_b, sc_b, L);
+    free(c_b); free(s0_b); free(sc_b); free(kap);
+    return 0;
+}
+
+/* Bond stretches of a frozen displacement field (for inspection in tests). */
+int pdo_stretch(const pdo_problem *p, const double *u, double *s_out)
+{
+    for (int64_t b = 0; b < p->n_bonds; ++b) {
+        int32_t i = p->bond_i[b], j = p->bond_j[b];
+        const double *xi = p->xi + 3 * b;
+        double y[3];
+        for (int d = 0; d < 3; ++d) y[d] = xi[d] + (u[3 * j + d] - u[3 * i + d]);
+        double ylen = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+        double xlen = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+        s_out[b] = (ylen - xlen) / xlen;
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------- time loop */
+
+/* Damped velocity-Verlet with displacement control.  Per step n = 0..N-1:
+ *   1. free DOFs: v += (dt / 2 rho) (L - damping v)
+ *   2. all DOFs:  u += dt v
+ *   3. supports: u_z = 0, v_z = 0; load pad: u_z = -(n+1) du, v_z = -du / dt
+ *   4. L = force(u), damage history updated
+ *   5. free DOFs: v = (v + (dt / 2 rho) L) / (1 + damping dt / 2 rho)
+ *   6. R = -sum over supports of L_z V; Q = max R, nstar = first argmax (1-based)
+ * u_init / v_init / kappa_init may be NULL (undamaged body at rest).
+ * Outputs may be NULL except Q. */
+int pdo_run(const pdo_problem *p, const double *u_init, const double *v_init,
+            const double *kappa_init, double *Q_out, int64_t *nstar_out, double *R_hist,
+            double *u_out, double *v_out, double *kappa_out)
+{
+    int64_t M = p->n_nodes, nb = p->n_bonds;
+    double *u = calloc(3 * M, sizeof(double)), *v = calloc(3 * M, sizeof(double));
+    double *L = calloc(3 * M, sizeof(double));
+    double *kappa = malloc(sizeof(double) * nb);
+    double *c_b = malloc(sizeof(double) * nb), *s0_b = malloc(sizeof(double) * nb),
+           *sc_b = malloc(sizeof(double) * nb);
+    unsigned char *fixed_z = calloc(M, 1);
+    if (!u || !v || !L || !kappa || !c_b || !s0_b || !sc_b || !fixed_z) return -2;
+    if (u_init) memcpy(u, u_init, sizeof(double) * 3 * M);
+    if (v_init) memcpy(v, v_init, sizeof(double) * 3 * M);
+    for (int64_t b = 0; b < nb; ++b) kappa[b] = kappa_init ? kappa_init[b] : -INFINITY;
+    bond_params(p, c_b, s0_b, sc_b);
+    for (int64_t a = 0; a < p->n_support; ++a) fixed_z[p->support[a]] = 1;
+    for (int64_t a = 0; a < p->n_load; ++a) fixed_z[p->load[a]] = 1;
+
+    /* the initial force of the (possibly pre-displaced) body */
+    force_eval(p, u, kappa, c_b, s0_b, sc_b, L);
+
+    double h = p->dt / (2.0 * p->rho);
+    double Q = -INFINITY;
+    int64_t nstar = 0;
+    for (int64_t n = 0; n < p->n_steps; ++n) {
+        for (int64_t i = 0; i < M; ++i)
+            for (int d = 0; d < 3; ++d) {
+                if (d == 2 && fixed_z[i]) continue;
+                v[3 * i + d] += h * (L[3 * i + d] - p->damping * v[3 * i + d]);
+            }
+        for (int64_t i = 0; i < 3 * M; ++i) u[i] += p->dt * v[i];
+        for (int64_t a = 0; a < p->n_support; ++a) {
+            u[3 * p->support[a] + 2] = 0.0;
+            v[3 * p->support[a] + 2] = 0.0;
+        }
+        for (int64_t a = 0; a < p->n_load; ++a) {
+            u[3 * p->load[a] + 2] = p->load_offset - (double)(n + 1) * p->du;
+            v[3 * p->load[a] + 2] = -p->du / p->dt;
+        }
+        force_eval(p, u, kappa, c_b, s0_b, sc_b, L);
+        for (int64_t i = 0; i < M; ++i)
+            for (int d = 0; d < 3; ++d) {
+                if (d == 2 && fixed_z[i]) continue;
+                v[3 * i + d] = (v[3 * i + d] + h * L[3 * i + d]) / (1.0 + p->damping * h);
+            }
+        double R = 0.0;
+        for (int64_t a = 0; a < p->n_support; ++a) R -= L[3 * p->support[a] + 2] * p->volume;
+        if (R_hist) R_hist[n] = R;
+        if (R > Q) { Q = R; nstar = n + 1; }
+    }
+    *Q_out = Q;
+    if (nstar_out) *nstar_out = nstar;
+    if (u_out) memcpy(u_out, u, sizeof(double) * 3 * M);
+    if (v_out) memcpy(v_out, v, sizeof(double) * 3 * M);
+    if (kappa_out) memcpy(kappa_out, kappa, sizeof(double) * nb);
+    free(u); free(v); free(L); free(kappa); free(c_b); free(s0_b); free(sc_b); free(fixed_z);
+    return 0;
+}
