@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the batched peridynamic Monte-Carlo solve on one MI355X.
+
+Workload (default): the level-1 notched concrete beam (70 x 20 x 20 = 28,000
+nodes, 1,490,324 unique bonds after the notch cut), a batch of 64 samples
+whose per-node limit stretch is a lognormal field (mean s0, CoV 0.2) from a
+50-mode Karhunen-Loeve expansion of a squared-exponential Gaussian field
+(length scale 20 mm, seed 1), 8000 damped velocity-Verlet steps under the
+literal displacement control (5e-8 mm per step scaled to dx), FP32 bond work
+with compensated accumulation and an FP64 reaction.  One benchmark "step" is
+one whole batch solve (every sample, every time step) with the inputs already
+resident in device memory.
+
+value = unique bond updates per second (bonds x time steps x samples / s).
+Alongside: samples/s, the plain per-sample FP64 solve of the same beam, the
+cracking-load variant, the step kernel's roofline, and the FP64 CPU oracle on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point operations per bond direction of the FP32 path:
+# e = u_j - u_i (3), v.e (5), e.e (5), 2 v.e + e.e (2), |v|^2 + num (1),
+# |y| = y2 rsqrt(y2) (2), |v|(|y| + |v|) (2), s = num / den (1),
+# w = s / |y| (1), existence weight (1), y = v + e (3), G += w y (6),
+# compensated accumulation of the pair sums (12 per pair = 6 per direction).
+FLOPS_PER_BOND_DIR_F32 = 38
+FLOPS_PER_BOND_DIR_F64 = 32          # no compensation
+# Attainable vector peak for this code: packed FP32 instructions are not
+# used, so 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+PEAK_TFLOPS_F32 = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_TFLOPS_F64 = 78.6
+STEP_KERNEL_F32 = "step_kernel<float, true, false>"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("solver.hip", "pd_internal.h"):
+        with open(os.path.join(ROOT, "paper_2212_04415_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(per_launch_alg_bytes=None):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 PMC
+    summary, or None when it is missing or was taken on other kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_L1x64_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle on the host: one sample of the same beam and field,
+    timed over the first n steps (about 10-30 s of work)."""
+    import numpy as np
+    import workloads as W
+    from oracle import geometry as OG
+    from oracle import kl as OKL
+    from oracle import solver as OS
+    OS.build(force=False)
+    lv = W.level(1)
+    ob = OKL.Basis3D((lv.beam.length, lv.beam.thickness, lv.beam.depth), W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    pos = OG.node_positions(lv.shape, lv.dx)
+    xi = W.kl_coefficients(1, 1)
+    s0 = OKL.lognormal_field(ob, pos, xi, W.S0_MEAN, W.FIELD_COV)[0]
+    probe = OS.beam_problem(lv, s0=s0, n_steps=20)
+    t = time.perf_counter()
+    probe.run(want_state=False)
+    per_step = (time.perf_counter() - t) / 20
+    n = max(20, int(seconds_target / per_step))
+    prob = OS.beam_problem(lv, s0=s0, n_steps=n)
+    t = time.perf_counter()
+    prob.run(want_state=False)
+    dt = time.perf_counter() - t
+    return {"value": prob.n_bonds * n / dt, "unit": "bond-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 sample of the level-1 beam (seed-1 KL field), first {n} of {lv.n_steps} steps, "
+                      f"{dt:.1f} s, single-threaded C at -O2"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed batch solves")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the plain FP64 and cracking-load legs")
+    ap.add_argument("--time-steps", type=int, default=None,
+                    help="profiling only: time steps per batch solve (default: the workload's 8000)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="profiling only: run a plain 1 GiB device copy (for scaling HBM counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the batched solve runs on a single MI355X and this build "
+              "has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2212_04415_amd import beam as B
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
+
+    S = 64
+    lv = W.level(1)
+    if args.time_steps:
+        import dataclasses
+        lv = dataclasses.replace(lv, n_steps=args.time_steps)
+    mesh = B.Mesh.for_level(lv)
+    kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    xi = torch.tensor(W.kl_coefficients(1, S), dtype=torch.float64)
+    s0 = kl.lognormal(xi, W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
+    params = B.make_params(lv, precision="f32", accumulate="kahan")
+    item = B.BatchItem(mesh, params, S, s0)
+
+    for _ in range(args.warmup):
+        B.run_batch([item])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        outs = B.run_batch([item], stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    Q = outs[0][0].cpu().numpy()
+    assert np.all(np.isfinite(Q)) and int(outs[0][2].abs().sum()) == 0
+
+    bond_updates = mesh.n_bonds * lv.n_steps * S
+    value = bond_updates * args.steps / wall
+    launches = lv.n_steps * args.steps
+    avg_launch_s = gpu_s / launches
+    flops_per_launch = 2 * mesh.n_bonds * S * FLOPS_PER_BOND_DIR_F32
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    traffic = traffic_from_profiles()
+
+    line = {
+        "metric": "bond-updates/s and MLMC samples/s on 1 MI355X, batched FP32 vs plain FP64 at equal QoI error",
+        "value": value,
+        "unit": "bond-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched_fp32_L1x64", "nodes": mesh.n_nodes, "bonds": mesh.n_bonds,
+                   "samples": S, "time_steps": lv.n_steps, "dx_mm": lv.dx * 1e3,
+                   "field": "lognormal KL, 50 modes, l=20 mm, CoV 0.2, seed 1",
+                   "load_per_step_mm": lv.du * 1e3, "accumulation": "kahan", "reaction": "f64"},
+        "samples_per_s": S * args.steps / wall,
+        "time_step_us": avg_launch_s * 1e6,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS_F32, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS_F32,
+                     "traffic": traffic, "kernel": STEP_KERNEL_F32,
+                     "flops_per_launch": flops_per_launch, "avg_launch_us": avg_launch_s * 1e6},
+    }
+
+    if not args.no_extras:
+        # plain per-sample FP64 solve of sample 0's field
+        p64 = B.make_params(lv, precision="f64")
+        mesh.set_field(0, s0[0].double().cpu().numpy())
+        B.run(mesh, B.make_params(lv, precision="f64", n_steps=64))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r64 = B.run(mesh, p64)
+        dt64 = time.perf_counter() - t
+        mesh.set_field(0, None)
+        line["plain_fp64"] = {"samples_per_s": 1.0 / dt64, "bond_updates_per_s": mesh.n_bonds * lv.n_steps / dt64,
+                              "peak_rel_diff_vs_batched_sample0": abs(r64["Q"] - float(Q[0])) / abs(r64["Q"])}
+        line["speedup_vs_plain_fp64"] = line["samples_per_s"] / line["plain_fp64"]["samples_per_s"]
+        # cracking-load variant (400x the literal increment): damage localises
+        lvf = W.level(1, fracture=True)
+        itf = B.BatchItem(mesh, B.make_params(lvf), S, s0)
+        B.run_batch([itf])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        of = B.run_batch([itf])
+        torch.cuda.synchronize()
+        dtf = time.perf_counter() - t
+        qf = of[0][0].cpu().numpy()
+        line["fracture_variant"] = {"bond_updates_per_s": mesh.n_bonds * lvf.n_steps * S / dtf,
+                                    "samples_per_s": S / dtf, "peak_mean_N": float(qf.mean()),
+                                    "peak_cov": float(qf.std() / qf.mean()),
+                                    "load_per_step_mm": lvf.du * 1e3}
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * pd.h -- C ABI of the MI355X peridynamic MC/MLMC solver (libpdmi.so).
+ *
+ * The library runs the explicit bond-based peridynamic solve of a notched
+ * three-point-bending beam once per Monte-Carlo / multilevel-Monte-Carlo
+ * sample, on one AMD Instinct MI355X (gfx950), and reduces each run to its
+ * peak support reaction.  Paper: Hobbs, Rappel, Dodwell, "A probabilistic
+ * peridynamic framework with an application to the study of the statistical
+ * size effect" (arXiv 2212.04415).
+ *
+ * Conventions for every entry point:
+ *   - Return value: PD_OK (0) or a negative PD_E* code.  The message of the
+ *     last error on the calling thread is available from pd_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Units: SI (m, kg, s, N, Pa) in FP64 host scalars.
+ *   - Node order: cell-centred lattice, node (i, j, k) at ((i+1/2)dx,
+ *     (j+1/2)dx, (k+1/2)dx) with index i + nx (j + ny k) (x fastest).
+ *   - Handles (pd_mesh, pd_run_h, pd_kl) and every device array the library
+ *     allocates for them are owned by the library and released by the
+ *     matching pd_free_* call.  Buffers passed in by the caller stay owned by
+ *     the caller and must stay valid until the stream work that uses them has
+ *     completed.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Entry points marked "async" only enqueue work on that stream.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define PD_API __attribute__((visibility("default")))
+#else
+#define PD_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PD_OK = 0,
+    PD_EINVAL = -1,      /* invalid argument or size */
+    PD_ENOMEM = -2,      /* host or device allocation failed */
+    PD_EDEVICE = -3,     /* HIP runtime error, or the HIP device is missing */
+    PD_EUNSTABLE = -4,   /* dt above the explicit stability limit */
+    PD_ENONFINITE = -5,  /* a run produced a non-finite reaction */
+    PD_ESTATE = -6       /* call out of order (e.g. bonds not built) */
+};
+
+enum { PD_LAW_EXPLIN = 0, PD_LAW_TRILINEAR = 1 };
+enum { PD_FP32 = 0, PD_FP64 = 1 };
+enum { PD_ACC_KAHAN = 0, PD_ACC_PLAIN = 1 };
+enum { PD_FIELD_S0 = 0, PD_FIELD_C = 1 };
+enum { PD_DTYPE_F32 = 0, PD_DTYPE_F64 = 1 };
+
+typedef struct pd_mesh_s *pd_mesh;
+typedef struct pd_run_s *pd_run_h;
+typedef struct pd_kl_s *pd_kl;
+
+/* Beam geometry (paper section 6.2 set-up; section 2.1 horizon).
+ * The body is the box [0, extent[0]] x [0, extent[1]] x [0, extent[2]]
+ * (length, thickness, depth).  Each extent must be a whole number of dx.
+ * The horizon is delta = m_ratio * dx (paper: m = 3.14).  Supports are two
+ * pad_width x pad_width blocks on the bottom face centred on
+ * x = extent[0]/2 -+ span/2; the load pad is one block on the top face centred
+ * on x = extent[0]/2; every pad spans the whole thickness.  notch_depth > 0
+ * cuts every bond crossing the plane x = extent[0]/2 below that height. */
+typedef struct {
+    double extent[3];
+    double dx;
+    double m_ratio;
+    double span;
+    double notch_depth;
+    double pad_width;
+} pd_mesh_desc;
+
+/* Material, loading and numerics of a run.
+ * E: Young's modulus (micromodulus c = 12 E / (pi delta^4), appendix A);
+ * rho: density; GF: fracture energy; s0: homogeneous linear-elastic limit
+ * stretch (used when no per-node field is set); k, alpha: softening shape
+ * (appendix A); law: PD_LAW_*; damping: viscous damping coefficient
+ * (force density per velocity); dt: time step; du: load-pad displacement
+ * increment per step (the pad is at u_z = -n du after step n); n_steps;
+ * precision: PD_FP32 (FP32 bond work and Verlet state with compensated
+ * accumulation; FP64 reaction) or PD_FP64; accumulate: PD_ACC_KAHAN or
+ * PD_ACC_PLAIN (FP32 ablation); record_history: keep R^n for every step;
+ * checkpoint_every: adjoint checkpoint interval (0 = library default). */
+typedef struct {
+    double E, rho, GF, s0, k, alpha;
+    int32_t law;
+    double damping, dt, du;
+    int64_t n_steps;
+    int32_t precision;
+    int32_t accumulate;
+    int32_t record_history;
+    int32_t checkpoint_every;
+} pd_params;
+
+/* Sizes of a built mesh. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int64_t n_nodes;
+    int64_t n_bonds;        /* unique bonds after the notch cut (0 before pd_build_bonds) */
+    int64_t n_cut;          /* bonds removed by the notch */
+    int32_t n_support, n_load;
+    int32_t n_stencil;      /* neighbours of an interior node */
+    double delta;           /* horizon */
+} pd_mesh_info_t;
+
+/* Build the lattice and the support / load node sets (host only).
+ * Fails with PD_EINVAL if an extent is not a multiple of dx, the notch
+ * position or depth is not a multiple of dx/2, or a node centre lies on a pad
+ * face.  *out receives a new handle. */
+PD_API int pd_build_mesh(const pd_mesh_desc *desc, pd_mesh *out);
+
+/* Neighbourhoods |x' - x| <= delta (paper section 2.1, Eq. PD_Horizon) as a
+ * fixed integer-offset stencil, the notch cut, and the upload of the mesh's
+ * device tables.  Idempotent.  *n_bonds_out (nullable) receives the number
+ * of unique bonds. */
+PD_API int pd_build_bonds(pd_mesh m, int64_t *n_bonds_out);
+
+PD_API int pd_mesh_get_info(pd_mesh m, pd_mesh_info_t *info);
+
+/* Node ids of the support and load pads (host arrays of n_support / n_load
+ * int32 entries, caller-owned; either may be NULL). */
+PD_API int pd_mesh_get_pads(pd_mesh m, int32_t *support, int32_t *load);
+
+/* Per-node material field for the single-sample entry points (pd_run,
+ * pd_force_eval, pd_qoi_grad).  field: PD_FIELD_S0 (limit stretch) or
+ * PD_FIELD_C (micromodulus).  values: [n_samples][n_nodes] of dtype
+ * PD_DTYPE_F32/F64, on the device if on_device else on the host; the library
+ * copies them (async on stream when on_device).  values = NULL clears the
+ * field (back to the homogeneous pd_params value).  Bond values are endpoint
+ * means (s0_b = (s0_i + s0_j)/2, c_b likewise). */
+PD_API int pd_set_material_field(pd_mesh m, int32_t field, int64_t n_samples, const void *values,
+                          int32_t on_device, int32_t dtype, void *stream);
+
+/* One force evaluation on frozen displacement fields (section 2.1,
+ * Eq. PD_EOM_Dynamic): L_i = sum_j c_b (1 - d_b) s_ij e_ij V with undamaged
+ * bonds (d_b = 0).  u_host: [n_samples][n_nodes][3] displacements (m);
+ * L_host: [n_samples][n_nodes][3] force densities (N/m^3).  Host buffers;
+ * synchronous.  Uses the sample's s0 / c fields when set. */
+PD_API int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double *u_host,
+                  double *L_host, void *stream);
+
+/* One sample of the explicit solve (async).  Per step n = 0..N-1, on the
+ * free degrees of freedom: v += (dt/2rho)(L - damping v); u += dt v; then
+ * supports u_z = 0 and the load pad u_z = -(n+1) du; L = force(u) with the
+ * irreversible damage history; v = (v + (dt/2rho) L) / (1 + damping dt/2rho);
+ * R^{n+1} = -sum_{supports} L_z V; Q = max_n R^n (section 4 QoI: peak load).
+ * *out receives a run handle; read it with pd_qoi / pd_run_state. */
+PD_API int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out);
+
+/* Peak reaction Q (N), its first step n* (1-based) and optionally the
+ * reaction history R[n_steps] (needs record_history).  Synchronises the run's
+ * stream.  Returns PD_ENONFINITE if the run went non-finite. */
+PD_API int pd_qoi(pd_run_h r, double *peak, int64_t *peak_step, double *history);
+
+/* Final displacement u (m, [n_nodes][3]) and, optionally, the damage history
+ * kappa of every bond direction as the library stores it (largest stretch
+ * seen, [122][n_nodes] FP64, 0 where the bond never passed its limit
+ * stretch).  Host buffers; synchronises. */
+PD_API int pd_run_state(pd_run_h r, double *u_out, double *kappa_out);
+
+PD_API int pd_free_run(pd_run_h r);
+
+/* A batch of independent samples over one or more meshes (levels), run as
+ * one launch per time tick over every active (sample, node tile) work item,
+ * replayed from a captured HIP graph.  Items whose dt is an integer multiple
+ * of the finest dt step on the matching ticks.  Per item: s0 (device,
+ * [n_samples][n_nodes], dtype = field_dtype, NULL = homogeneous p->s0),
+ * c (device or NULL); outputs qoi (device FP64 [n_samples]), nstar (device
+ * int64 [n_samples], nullable), status (device int32 [n_samples], nullable;
+ * PD_OK or PD_ENONFINITE).  Async on stream; the caller's buffers must stay
+ * valid until it completes.  All items share precision and accumulate. */
+typedef struct {
+    pd_mesh mesh;
+    const pd_params *params;
+    int64_t n_samples;
+    const void *s0;
+    const void *c;
+    int32_t field_dtype;
+    double *qoi;
+    int64_t *nstar;
+    int32_t *status;
+} pd_batch_item;
+
+PD_API int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream);
+
+/* Gradient of the peak reaction Q = R^{n*} with respect to the per-node
+ * limit-stretch field s0 and micromodulus field c, by a hand-written
+ * discrete adjoint of the time loop with forward checkpoints every
+ * p->checkpoint_every steps.  s0_dev / c_dev: device FP64 [n_nodes]
+ * (nullable: homogeneous values).  dq_ds0_dev, dq_dc_dev: device FP64
+ * [n_nodes] outputs (either nullable).  *peak_out and *peak_step_out
+ * (nullable) receive Q and n*.  Synchronous on stream. */
+PD_API int pd_qoi_grad(pd_mesh m, const pd_params *p, const double *s0_dev, const double *c_dev,
+                double *dq_ds0_dev, double *dq_dc_dev, double *peak_out, int64_t *peak_step_out,
+                void *stream);
+
+/* Karhunen-Loeve basis of a unit-variance Gaussian field with correlation
+ * exp(-r^2 / (2 corr_len^2)) on the mesh's box (paper section 5, KL
+ * expansion): the n_modes largest separable eigenpairs, from an n_quad-point
+ * Gauss-Legendre Nystrom solve per axis, evaluated at the node centres and
+ * uploaded (FP64).  Each 1D eigenfunction is signed positive at x = 0; equal
+ * eigenvalue products (relative 1e-9) are ordered by their 1D indices. */
+PD_API int pd_kl_build(pd_mesh m, double corr_len, int32_t n_modes, int32_t n_quad, pd_kl *out);
+
+/* Eigenvalues of the selected modes (host FP64 [n_modes]). */
+PD_API int pd_kl_eigenvalues(pd_kl kl, double *lam_out);
+
+/* Lognormal field s0 = exp(mu + sigma g), g = sum_m sqrt(lambda_m) phi_m xi_m,
+ * sigma^2 = ln(1 + cov^2), mu = ln(mean) - sigma^2 / 2.  xi_dev: device FP64
+ * [n_samples][n_modes]; out_dev: device [n_samples][n_nodes] of out_dtype.
+ * Async. */
+PD_API int pd_kl_field(pd_kl kl, const double *xi_dev, int64_t n_samples, double mean, double cov,
+                void *out_dev, int32_t out_dtype, void *stream);
+
+PD_API int pd_kl_free(pd_kl kl);
+
+/* FP64 level sums of an MLMC level: Y = q_fine - q_coarse (q_coarse NULL:
+ * Y = q_fine), sums_dev[0] = N, [1] = sum Y, [2] = sum Y^2 (device FP64,
+ * overwritten).  Deterministic (fixed reduction order).  Async. */
+PD_API int pd_level_stats(const double *q_fine_dev, const double *q_coarse_dev, int64_t n,
+                   double *sums_dev, void *stream);
+
+PD_API int pd_free_mesh(pd_mesh m);
+
+/* Message of the last failed call on this thread ("" if none). */
+PD_API const char *pd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PD_H */

@@ -1,0 +1,194 @@
+"""Convenience wrappers over the C ABI for beam workloads (argument
+marshalling only; the solve runs in libpdmi's kernels)."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import pd
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Mesh:
+    """A built beam lattice (pd_build_mesh + pd_build_bonds)."""
+
+    def __init__(self, beam, dx: float, m_ratio: float = 3.14):
+        self.beam, self.dx = beam, dx
+        desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, beam.thickness, beam.depth), dx, m_ratio,
+                               beam.span, beam.notch_depth, beam.pad_width)
+        self.h = C.c_void_p()
+        pd.pd_build_mesh(C.byref(desc), C.byref(self.h))
+        nb = C.c_int64()
+        pd.pd_build_bonds(self.h, C.byref(nb))
+        info = pd.pd_mesh_info_t()
+        pd.pd_mesh_get_info(self.h, C.byref(info))
+        self.info = info
+        self.shape = (info.nx, info.ny, info.nz)
+        self.n_nodes = int(info.n_nodes)
+        self.n_bonds = int(info.n_bonds)
+        sup = np.zeros(info.n_support, dtype=np.int32)
+        ld = np.zeros(info.n_load, dtype=np.int32)
+        pd.pd_mesh_get_pads(self.h, sup.ctypes.data, ld.ctypes.data)
+        self.support, self.load = sup, ld
+
+    @classmethod
+    def for_level(cls, level, m_ratio: float = 3.14):
+        return cls(level.beam, level.dx, m_ratio)
+
+    def set_field(self, field: int, values: Optional[np.ndarray]):
+        if values is None:
+            pd.pd_set_material_field(self.h, field, 0, None, 0, pd.PD_DTYPE_F64, None)
+            return
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        n = v.size // self.n_nodes
+        pd.pd_set_material_field(self.h, field, n, v.ctypes.data, 0, pd.PD_DTYPE_F64, None)
+
+    def close(self):
+        if self.h:
+            pd.pd_free_mesh(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(level=None, *, precision="f32", accumulate="kahan", E=None, rho=None, GF=None, s0=None,
+                k=None, alpha=None, law=None, damping=None, dt=None, du=None, n_steps=None,
+                record_history=False, checkpoint_every=0) -> pd.pd_params:
+    import workloads as W
+    p = pd.pd_params()
+    p.E = W.E_MODULUS if E is None else E
+    p.rho = W.DENSITY if rho is None else rho
+    p.GF = W.FRACTURE_ENERGY if GF is None else GF
+    p.s0 = W.S0_MEAN if s0 is None else s0
+    p.k = W.SOFT_K if k is None else k
+    p.alpha = W.SOFT_ALPHA if alpha is None else alpha
+    p.law = (level.law if level is not None else W.LAW_TRILINEAR) if law is None else law
+    p.damping = W.DAMPING if damping is None else damping
+    p.dt = level.dt if dt is None else dt
+    p.du = level.du if du is None else du
+    p.n_steps = level.n_steps if n_steps is None else n_steps
+    p.precision = {"f32": pd.PD_FP32, "f64": pd.PD_FP64}[precision]
+    p.accumulate = {"kahan": pd.PD_ACC_KAHAN, "plain": pd.PD_ACC_PLAIN}[accumulate]
+    p.record_history = 1 if record_history else 0
+    p.checkpoint_every = checkpoint_every
+    return p
+
+
+def force_eval(mesh: Mesh, params, u: np.ndarray) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, mesh.n_nodes, 3)
+    L = np.zeros_like(u)
+    pd.pd_force_eval(mesh.h, C.byref(params), u.shape[0], u.ctypes.data, L.ctypes.data, None)
+    return L
+
+
+def run(mesh: Mesh, params, stream=None, want_state=False):
+    """One sample (uses the mesh's single-sample fields).  Returns a dict with
+    Q, nstar, R (when record_history) and u, kappa (when want_state)."""
+    h = C.c_void_p()
+    pd.pd_run(mesh.h, C.byref(params), _stream_ptr(stream) if stream is not None else None, C.byref(h))
+    try:
+        Q = C.c_double()
+        ns = C.c_int64()
+        R = np.zeros(max(params.n_steps, 1)) if params.record_history else None
+        pd.pd_qoi(h, C.byref(Q), C.byref(ns), R.ctypes.data if R is not None else None)
+        out = dict(Q=Q.value, nstar=ns.value, R=R)
+        if want_state:
+            u = np.zeros((mesh.n_nodes, 3))
+            kap = np.zeros((122, mesh.n_nodes))
+            pd.pd_run_state(h, u.ctypes.data, kap.ctypes.data)
+            out["u"], out["kappa"] = u, kap
+        return out
+    finally:
+        pd.pd_free_run(h)
+
+
+@dataclass
+class BatchItem:
+    mesh: Mesh
+    params: pd.pd_params
+    n_samples: int
+    s0: object = None          # torch tensor [S][M] on the device, or None
+    c: object = None
+
+
+def run_batch(items: Sequence[BatchItem], stream=None):
+    """Returns a list of (Q, nstar, status) torch tensors, one triple per item."""
+    import torch
+    dev = torch.device("cuda")
+    arr = (pd.pd_batch_item * len(items))()
+    outs, keep = [], []
+    for i, it in enumerate(items):
+        Q = torch.empty(it.n_samples, dtype=torch.float64, device=dev)
+        ns = torch.empty(it.n_samples, dtype=torch.int64, device=dev)
+        st = torch.empty(it.n_samples, dtype=torch.int32, device=dev)
+        dtype = pd.PD_DTYPE_F64
+        for f in (it.s0, it.c):
+            if f is not None:
+                assert f.is_cuda and f.is_contiguous() and f.shape == (it.n_samples, it.mesh.n_nodes)
+                dtype = pd.PD_DTYPE_F32 if f.dtype == torch.float32 else pd.PD_DTYPE_F64
+        if it.s0 is not None and it.c is not None:
+            assert it.s0.dtype == it.c.dtype
+        keep.append(it.params)
+        arr[i] = pd.pd_batch_item(it.mesh.h, C.pointer(it.params), it.n_samples,
+                                  it.s0.data_ptr() if it.s0 is not None else None,
+                                  it.c.data_ptr() if it.c is not None else None, dtype,
+                                  Q.data_ptr(), ns.data_ptr(), st.data_ptr())
+        outs.append((Q, ns, st))
+    pd.pd_run_batch(arr, len(items), _stream_ptr(stream))
+    return outs
+
+
+class KL:
+    """Karhunen-Loeve basis of a mesh (pd_kl_build)."""
+
+    def __init__(self, mesh: Mesh, corr_len: float, n_modes: int = 50, n_quad: int = 256):
+        self.mesh, self.n_modes = mesh, n_modes
+        self.h = C.c_void_p()
+        pd.pd_kl_build(mesh.h, corr_len, n_modes, n_quad, C.byref(self.h))
+
+    def eigenvalues(self):
+        lam = np.zeros(self.n_modes)
+        pd.pd_kl_eigenvalues(self.h, lam.ctypes.data)
+        return lam
+
+    def lognormal(self, xi, mean: float, cov: float, dtype=None, stream=None):
+        import torch
+        dtype = torch.float64 if dtype is None else dtype
+        xi = xi.to(device="cuda", dtype=torch.float64).contiguous()
+        out = torch.empty((xi.shape[0], self.mesh.n_nodes), dtype=dtype, device="cuda")
+        pd.pd_kl_field(self.h, xi.data_ptr(), xi.shape[0], mean, cov, out.data_ptr(),
+                       pd.PD_DTYPE_F64 if dtype == torch.float64 else pd.PD_DTYPE_F32, _stream_ptr(stream))
+        return out
+
+    def close(self):
+        if self.h:
+            pd.pd_kl_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def level_stats(q_fine, q_coarse=None, stream=None):
+    """FP64 (N, sum Y, sum Y^2) of one MLMC level as a device tensor."""
+    import torch
+    sums = torch.empty(3, dtype=torch.float64, device="cuda")
+    pd.pd_level_stats(q_fine.data_ptr(), q_coarse.data_ptr() if q_coarse is not None else None,
+                      q_fine.numel(), sums.data_ptr(), _stream_ptr(stream))
+    return sums

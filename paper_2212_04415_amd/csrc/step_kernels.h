@@ -1,0 +1,605 @@
+// Device code of one explicit time step of the bond-based peridynamic solve.
+//
+// A step evaluates, for every node of every sample, the bond forces over its
+// 122-point horizon (paper section 2.1, Eq. PD_Force_Function and
+// Eq. PD_EOM_Dynamic; appendix A, Eq. exp_scalar_force and
+// Eq. exp_damage_parameter), sums them with compensated accumulation, closes
+// the damped velocity-Verlet step and opens the next one.  The first block of
+// each sample also forms the FP64 reaction of the previous step and keeps the
+// running peak (section 4: the quantity of interest is the peak load).
+//
+// Layout (per sample; all arrays sample-major):
+//   u     : padded grid of (u_x, u_y, u_z, flag) in units of dx, ping-pong.
+//           kHalo ghost layers per face hold flag 0; flag +1 marks a node
+//           whose bonds are all below their limit stretch, -1 a node with a
+//           damaged bond.  |flag| is the neighbour-existence weight.
+//   vh    : half-step velocity (dx/s); in FP32 also the compensation terms of
+//           vh and u;
+//   hist  : largest stretch of each bond direction, [122][M], touched only by
+//           nodes with a damaged bond (0 until the bond passes its limit);
+//   s0pad : padded per-node limit stretch (+inf on ghosts); thr: per-node
+//           lower bound of the limit stretches of its bonds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+#include "pd_internal.h"
+
+#ifndef PD_BLOCK
+#define PD_BLOCK 256
+#endif
+#ifndef PD_PIPE_DEPTH
+#define PD_PIPE_DEPTH 4
+#endif
+
+namespace pdmi {
+
+constexpr int kBlock = PD_BLOCK;
+constexpr int kXcds = 8;
+
+// brick of nodes per block on the LDS path, and its tile with the halo
+constexpr int kBX = 16, kBY = 4, kBZ = 4;
+static_assert(kBX * kBY * kBZ == kBlock, "brick must match the block");
+constexpr int kLX = kBX + 2 * kHalo, kLY = kBY + 2 * kHalo, kLZ = kBZ + 2 * kHalo;
+constexpr int kLXY = kLX * kLY;
+constexpr int kTileN = kLX * kLY * kLZ;
+
+// sqrt(n) for the squared lengths that occur in the stencil
+constexpr double kSqrtInt[10] = {0.0, 1.0, 1.4142135623730951, 1.7320508075688772, 2.0,
+                                 2.23606797749979, 2.449489742783178, 2.6457513110645907,
+                                 2.8284271247461903, 3.0};
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using t = float4; };
+template <> struct Vec4<double> { using t = double4; };
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ float expx(float x) { return __expf(x); }
+__device__ __forceinline__ double expx(double x) { return exp(x); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+struct StepParams {
+    using V4 = typename Vec4<T>::t;
+    const V4 *u_cur;
+    V4 *u_next;
+    V4 *vh;
+    V4 *cu;             // FP32 only: compensation of u
+    V4 *cvh;            // FP32 only: compensation of vh
+    T *hist;            // [S][122][M]
+    const T *s0pad;     // [S][P]
+    const T *thr;       // [S][M]
+    const T *cpad;      // [S][P] c / c_ref, or null
+    const NodeInfo *info;
+    const uint4 *cut;
+    double *rf;         // [2][S][nsup] support-node force sums, by step parity
+    int64_t rf_stride;  // S * nsup
+    double *L_out;      // force-only mode: [S][M][3]
+    const int64_t *step_base;  // [S] first step of the current replay chunk
+    int k_local;               // step within the chunk (fixed per launch)
+    int64_t n_steps;
+    double *Q;                 // [S] running peak reaction
+    int64_t *nstar;            // [S] step of the peak (1-based)
+    int32_t *status;           // [S]
+    double *hist_R;            // [S][n_steps] or null
+    double Rscale;             // R = -Rscale * sum of support-node G_z
+    int64_t P, M, PXY;
+    int64_t tiles, n_items;    // tiles per sample, samples * tiles
+    int nx, ny, nz, PX, PY, PZ, nsup;
+    int nbx, nby;              // bricks along x and y (LDS path)
+    int force_only;
+    T two_d_b, two_d_g, dt, vload;  // integrator in units of dx
+    double du_s;                    // load increment in units of dx
+    T gamma_rel, k, alpha, inv1mek, inv1pa;
+    int law;
+    double LV;                      // c_ref V: force density per unit G
+};
+
+template <typename T, bool KAHAN>
+struct Acc3 {
+    T x, y, z, cx, cy, cz;
+    __device__ __forceinline__ void zero() { x = y = z = cx = cy = cz = T(0); }
+    __device__ __forceinline__ void add(T px, T py, T pz)
+    {
+        if constexpr (KAHAN) {
+            kahan(x, cx, px);
+            kahan(y, cy, py);
+            kahan(z, cz, pz);
+        } else {
+            x += px;
+            y += py;
+            z += pz;
+        }
+    }
+    __device__ __forceinline__ static void kahan(T &s, T &c, T v)
+    {
+        T yv = v - c;
+        T t = s + yv;
+        c = (t - s) - yv;
+        s = t;
+    }
+    __device__ __forceinline__ T gx() const { return KAHAN ? x - cx : x; }
+    __device__ __forceinline__ T gy() const { return KAHAN ? y - cy : y; }
+    __device__ __forceinline__ T gz() const { return KAHAN ? z - cz : z; }
+};
+
+// ---------------------------------------------------------------- stretch
+// For a bond with lattice offset v (units of dx) and e = u_j - u_i,
+// |v + e|^2 = |v|^2 + num with num = 2 v.e + e.e = sum_c e_c (2 v_c + e_c), and
+// the stretch (|xi + eta| - |xi|)/|xi| equals num / (|v| (|v + e| + |v|)),
+// which has no cancellation.  The operation sequence is spelled out (the
+// library is built without floating-point contraction) so that the two ends
+// of a bond, and the compile-time and run-time offset paths, produce
+// bit-identical results: 2 v_c + e_c is exact up to its rounding, which is
+// symmetric under (v, e) -> (-v, -e), and terms with v_c = 0 reduce to
+// e_c * e_c on both paths.
+template <int C, int SIGN, typename T>
+__device__ __forceinline__ T term_c(T e)
+{
+    if constexpr (C == 0) return e;
+    else return T(2 * SIGN * C) + e;
+}
+
+template <typename T, int VX, int VY, int VZ, int SIGN>
+__device__ __forceinline__ T num_c(const typename Vec4<T>::t &ui, const typename Vec4<T>::t &uj, T &ex, T &ey,
+                                   T &ez)
+{
+    ex = uj.x - ui.x;
+    ey = uj.y - ui.y;
+    ez = uj.z - ui.z;
+    T n = ex * term_c<VX, SIGN>(ex);
+    n = fma_(ey, term_c<VY, SIGN>(ey), n);
+    return fma_(ez, term_c<VZ, SIGN>(ez), n);
+}
+
+template <typename T>
+__device__ __forceinline__ T num_rt(const typename Vec4<T>::t &ui, const typename Vec4<T>::t &uj, int vx, int vy,
+                                    int vz, T &ex, T &ey, T &ez)
+{
+    ex = uj.x - ui.x;
+    ey = uj.y - ui.y;
+    ez = uj.z - ui.z;
+    T n = ex * (vx == 0 ? ex : T(2 * vx) + ex);
+    n = fma_(ey, vy == 0 ? ey : T(2 * vy) + ey, n);
+    return fma_(ez, vz == 0 ? ez : T(2 * vz) + ez, n);
+}
+
+// closed-form stretch and 1/|v + e| from num
+template <typename T>
+__device__ __forceinline__ T stretch_from_num(T num, T V2, T VL, T &ry)
+{
+    T y2 = V2 + num;
+    ry = rsq(y2);
+    T den = fma_(VL, y2 * ry, V2);
+    return quot(num, den);
+}
+
+// 1 - d for the largest stretch kap of a bond with limit s0 and critical sc
+// (appendix A, Eq. exp_damage_parameter; piecewise-linear envelope otherwise)
+template <typename T>
+__device__ __forceinline__ T keep_fraction(const StepParams<T> &a, T kap, T s0, T sc)
+{
+    if (kap >= sc) return T(0);
+    T t = quot(kap - s0, sc - s0);
+    if (a.law == PD_LAW_EXPLIN) {
+        T br = T(1) - (T(1) - expx(-a.k * t)) * a.inv1mek + a.alpha * (T(1) - t);
+        return quot(s0, kap) * br * a.inv1pa;
+    }
+    // envelope c s0 at s0, 0.2 c s0 at s1 = s0 + 0.2 (sc - s0), 0 at sc
+    T f = (t <= T(0.2)) ? s0 * (T(1) - T(4) * t) : s0 * (T(0.25) * (T(1) - t));
+    return quot(f, kap);
+}
+
+// ---------------------------------------------------------------- neighbour sources
+// element of a per-sample array at (lane base + uniform offset), addressed as a
+// scalar base plus a 32-bit per-lane byte offset
+template <typename E>
+__device__ __forceinline__ E ld(const E *base, int64_t off, uint32_t lane_bytes)
+{
+    return *(const E *)((const char *)(base + off) + lane_bytes);
+}
+
+// displacement of the neighbour at lattice offset v, from the padded grid
+template <typename T>
+struct GlobalSrc {
+    using V4 = typename Vec4<T>::t;
+    const V4 *U;
+    uint32_t lb;
+    int64_t PX, PXY;
+    template <int X, int Y, int Z> __device__ __forceinline__ V4 get() const
+    {
+        return ld(U, (int64_t)X + (int64_t)Y * PX + (int64_t)Z * PXY, lb);
+    }
+    __device__ __forceinline__ V4 get(int x, int y, int z) const
+    {
+        return ld(U, (int64_t)x + (int64_t)y * PX + (int64_t)z * PXY, lb);
+    }
+};
+
+// ... from the block's LDS tile (brick plus halo)
+template <typename T>
+struct LdsSrc {
+    using V4 = typename Vec4<T>::t;
+    const V4 *tile;
+    int c;
+    template <int X, int Y, int Z> __device__ __forceinline__ V4 get() const
+    {
+        return tile[c + X + kLX * Y + kLXY * Z];
+    }
+    __device__ __forceinline__ V4 get(int x, int y, int z) const { return tile[c + x + kLX * y + kLXY * z]; }
+};
+
+// ---------------------------------------------------------------- pipelining
+// The 61 offset pairs are unrolled with compile-time offsets.  Loads of pair
+// K + D are issued before the arithmetic of pair K, and a scheduling fence per
+// pair keeps the compiler from hoisting all 122 neighbour loads (which would
+// exhaust the register file).
+template <int K, int N, int D, typename R, typename LoadF, typename CompF>
+__device__ __forceinline__ void pipe_step(R (&ring)[D], LoadF &load, CompF &comp)
+{
+    if constexpr (K < N) {
+        __builtin_amdgcn_sched_barrier(0);
+        R cur = ring[K % D];
+        if constexpr (K + D < N) ring[K % D] = load(std::integral_constant<int, K + D>{});
+        comp(std::integral_constant<int, K>{}, cur);
+        pipe_step<K + 1, N, D>(ring, load, comp);
+    }
+}
+
+template <int D, typename R, typename LoadF, typename CompF, int... I>
+__device__ __forceinline__ void pipeline(LoadF &load, CompF &comp, std::integer_sequence<int, I...>)
+{
+    R ring[D];
+    ((ring[I] = load(std::integral_constant<int, I>{})), ...);
+    pipe_step<0, kHalfStencil, D>(ring, load, comp);
+}
+
+template <typename T> struct FastLoad {
+    typename Vec4<T>::t a, b;
+    T ca, cb;
+};
+
+// ---------------------------------------------------------------- fast path
+// All bonds of the node are known to be below their limit stretch (d = 0);
+// flag is raised when a bond may have reached the node's lower bound of limit
+// stretches (or is compressed beyond 2^-13), and the node is then redone on
+// the history path.
+//
+// In FP32 the stretch and the force weight w = s / |v + e| of an undamaged
+// bond are evaluated without square root or division: with x = num / (2|v|^2),
+// |v + e| = |v| sqrt(1 + 2x), so
+//   s = sqrt(1 + 2x) - 1 <= x,
+//   w = (1 - (1 + 2x)^(-1/2)) / |v| = (x / |v|)(1 - 3/2 x + 5/2 x^2 - ...).
+// On this path |x| < 2^-13 (larger tensions are flagged through s <= x,
+// larger compressions explicitly), so keeping two terms leaves a relative
+// error below 5/2 * 2^-26 = 3.7e-8, under FP32 rounding (2^-24 = 6e-8).  FP64
+// and the history path use the closed form.
+constexpr double kSeriesBound = 1.0 / 8192;
+
+template <typename T, bool KAHAN, bool HAS_C, typename Src>
+__device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src, const T *__restrict__ Cp,
+                                          uint32_t lb1, const typename Vec4<T>::t &ui, T ci, T thr,
+                                          Acc3<T, KAHAN> &acc, bool &flag)
+{
+    auto load = [&](auto kc) {
+        constexpr Off v = kHalf.v[decltype(kc)::value];
+        FastLoad<T> r;
+        r.a = src.template get<v.x, v.y, v.z>();
+        r.b = src.template get<-v.x, -v.y, -v.z>();
+        if constexpr (HAS_C) {
+            const int64_t off = (int64_t)v.x + (int64_t)v.y * a.PX + (int64_t)v.z * a.PXY;
+            r.ca = ld(Cp, off, lb1);
+            r.cb = ld(Cp, -off, lb1);
+        } else {
+            r.ca = r.cb = T(1);
+        }
+        return r;
+    };
+    T hi = T(-1), lo = T(1);   // extreme weighted x (FP32) or stretch (FP64) seen
+    T pend_x = T(0), pend_y = T(0), pend_z = T(0);   // partial sum of the current group of pairs
+    auto comp_pair = [&](auto kc, const FastLoad<T> &r) {
+        constexpr int K = decltype(kc)::value;
+        constexpr Off v = kHalf.v[K];
+        constexpr int V2 = v.x * v.x + v.y * v.y + v.z * v.z;
+        T eax, eay, eaz, ebx, eby, ebz, wa, wb;
+        const T na = num_c<T, v.x, v.y, v.z, 1>(ui, r.a, eax, eay, eaz);
+        const T nb = num_c<T, v.x, v.y, v.z, -1>(ui, r.b, ebx, eby, ebz);
+        if constexpr (sizeof(T) == 4) {
+            const T xa = na * T(0.5 / V2), xb = nb * T(0.5 / V2);
+            const T xwa = xa * fabs(r.a.w), xwb = xb * fabs(r.b.w);
+            hi = fmax(hi, fmax(xwa, xwb));
+            lo = fmin(lo, fmin(xwa, xwb));
+            constexpr T IV = T(1.0 / kSqrtInt[V2]);
+            constexpr T IV15 = T(-1.5 / kSqrtInt[V2]);
+            wa = xwa * fma_(xa, IV15, IV);
+            wb = xwb * fma_(xb, IV15, IV);
+        } else {
+            T rya, ryb;
+            const T sa = stretch_from_num(na, T(V2), T(kSqrtInt[V2]), rya) * fabs(r.a.w);
+            const T sb = stretch_from_num(nb, T(V2), T(kSqrtInt[V2]), ryb) * fabs(r.b.w);
+            hi = fmax(hi, fmax(sa, sb));
+            wa = sa * rya;
+            wb = sb * ryb;
+        }
+        if constexpr (HAS_C) {
+            wa = wa * (T(0.5) * (ci + r.ca));
+            wb = wb * (T(0.5) * (ci + r.cb));
+        }
+        // wa (v + ea) + wb (-v + eb) = (wa - wb) v + wa ea + wb eb: the large
+        // symmetric parts cancel exactly before they are scaled.  Pair sums
+        // are chained into the group's partial sum, and each group of four
+        // pairs (eight bonds) enters the compensated accumulator once.
+        constexpr int G = 4;
+        constexpr bool first = (K % G == 0);
+        const T dw = wa - wb;
+        auto part = [&](auto cc, T ea, T eb, T pend) {
+            constexpr int C = decltype(cc)::value;
+            const T base = first ? wb * eb : fma_(wb, eb, pend);
+            if constexpr (C == 0) return fma_(wa, ea, base);
+            else return fma_(wa, ea, fma_(dw, T(C), base));
+        };
+        pend_x = part(std::integral_constant<int, v.x>{}, eax, ebx, pend_x);
+        pend_y = part(std::integral_constant<int, v.y>{}, eay, eby, pend_y);
+        pend_z = part(std::integral_constant<int, v.z>{}, eaz, ebz, pend_z);
+        if constexpr (K % G == G - 1 || K + 1 == kHalfStencil) acc.add(pend_x, pend_y, pend_z);
+    };
+    constexpr int D = sizeof(T) == 4 ? PD_PIPE_DEPTH : 2;
+    pipeline<D, FastLoad<T>>(load, comp_pair, std::make_integer_sequence<int, D>{});
+    if constexpr (sizeof(T) == 4) flag = (hi > fmin(thr, T(kSeriesBound))) || (lo < T(-kSeriesBound));
+    else flag = hi > thr;
+}
+
+// ---------------------------------------------------------------- history path
+struct SlotEntry {
+    int x, y, z, len2;
+};
+
+struct SlotTable {
+    SlotEntry e[kStencil];
+};
+
+constexpr SlotTable make_slot_table()
+{
+    SlotTable t{};
+    for (int k = 0; k < kStencil; ++k) {
+        Off o = kHalf.v[k % kHalfStencil];
+        int sg = k < kHalfStencil ? 1 : -1;
+        t.e[k] = SlotEntry{sg * o.x, sg * o.y, sg * o.z, o.x * o.x + o.y * o.y + o.z * o.z};
+    }
+    return t;
+}
+
+static __constant__ SlotTable c_slots = make_slot_table();
+static __constant__ double c_sqrt_int[10] = {0.0, 1.0, 1.4142135623730951, 1.7320508075688772, 2.0,
+                                             2.23606797749979, 2.449489742783178, 2.6457513110645907,
+                                             2.8284271247461903, 3.0};
+
+// Every bond with its damage history: bonds past their limit stretch keep
+// the largest stretch they have seen in hist (never decreasing, so damage
+// never heals); notch-cut bonds and ghost neighbours contribute nothing.
+template <typename T, bool KAHAN, bool HAS_C, typename Src>
+__device__ __forceinline__ void hist_loop(const StepParams<T> &a, const Src &src, const T *__restrict__ S0,
+                                          const T *__restrict__ Cp, T *__restrict__ Hs, uint32_t lb1,
+                                          int64_t node, const typename Vec4<T>::t &ui, T s0i, T ci, uint4 cm,
+                                          Acc3<T, KAHAN> &acc, bool &dirty)
+{
+    using V4 = typename Vec4<T>::t;
+    const uint32_t lbh = (uint32_t)node * (uint32_t)sizeof(T);
+    for (int k = 0; k < kStencil; ++k) {
+        const SlotEntry e = c_slots.e[k];
+        const V4 uj = src.get(e.x, e.y, e.z);
+        const uint32_t bits = k < 32 ? cm.x : k < 64 ? cm.y : k < 96 ? cm.z : cm.w;
+        if (uj.w == T(0) || ((bits >> (k & 31)) & 1u)) continue;
+        const int64_t off = (int64_t)e.x + (int64_t)e.y * a.PX + (int64_t)e.z * a.PXY;
+        T ex, ey, ez, ry;
+        const T num = num_rt<T>(ui, uj, e.x, e.y, e.z, ex, ey, ez);
+        const T s = stretch_from_num(num, T(e.len2), T(c_sqrt_int[e.len2]), ry);
+        const T s0b = T(0.5) * (s0i + ld(S0, off, lb1));
+        T *H = (T *)((char *)(Hs + (int64_t)k * a.M) + lbh);
+        T kap = *H;
+        if (s > kap && s > s0b) {
+            kap = s;
+            *H = s;
+        }
+        const T cb = HAS_C ? T(0.5) * (ci + ld(Cp, off, lb1)) : T(1);
+        T keep = T(1);
+        if (kap > s0b) {
+            dirty = true;
+            const T sc = s0b + quot(a.gamma_rel, cb * s0b);
+            keep = keep_fraction(a, kap, s0b, sc);
+        }
+        const T w = keep * s * ry * cb;
+        acc.add(w * (T(e.x) + ex), w * (T(e.y) + ey), w * (T(e.z) + ez));
+    }
+}
+
+// ---------------------------------------------------------------- integrator
+template <typename T, bool KAHAN>
+__device__ __forceinline__ void kick_drift(const StepParams<T> &a, T G, T &vh, T &cvh, T &u, T &cu)
+{
+    // vh^{n+1} = vh^n + 2D (b G - g vh^n);  u^{n+2} = u^{n+1} + dt vh^{n+1}
+    T dv = fma_(a.two_d_b, G, -(a.two_d_g * vh));
+    if constexpr (KAHAN) {
+        Acc3<T, true>::kahan(vh, cvh, dv);
+        Acc3<T, true>::kahan(u, cu, a.dt * vh);
+    } else {
+        vh += dv;
+        u += a.dt * vh;
+    }
+}
+
+// Reaction of step n-1, formed at the start of step n by the first block of
+// each sample: the support-node forces of a step are written to one half of
+// a double buffer and summed in FP64 by the next launch, so the kernel
+// boundary orders the writes before the reads (no device-wide fences).  The
+// sum runs in a fixed order (a strided pass per thread, then a fixed tree),
+// so R does not depend on scheduling.
+template <typename T>
+__device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int sample, int64_t n)
+{
+    __shared__ double part[kBlock];
+    const int64_t prev = n - 1;
+    double sum = 0.0;
+    const double *rf = a.rf + ((int64_t)(prev & 1) * a.rf_stride) + (int64_t)sample * a.nsup;
+    for (int i = threadIdx.x; i < a.nsup; i += kBlock) sum += rf[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double R = -a.Rscale * part[0];
+        if (!isfinite(R)) a.status[sample] = PD_ENONFINITE;
+        if (R > a.Q[sample]) {
+            a.Q[sample] = R;
+            a.nstar[sample] = prev + 1;
+        }
+        if (a.hist_R) a.hist_R[(int64_t)sample * a.n_steps + prev] = R;
+    }
+}
+
+// Forces and Verlet update of one node, given its neighbour source.
+template <typename T, bool KAHAN, bool HAS_C, typename Src>
+__device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src, int sample, int64_t n, int64_t node,
+                                          int64_t p, const typename Vec4<T>::t &ui)
+{
+    using V4 = typename Vec4<T>::t;
+    const T *__restrict__ S0 = a.s0pad + (int64_t)sample * a.P;
+    const T *__restrict__ Cp = HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr;
+    const uint32_t lb1 = (uint32_t)p * (uint32_t)sizeof(T);
+    const int64_t sm = (int64_t)sample * a.M + node;
+    const NodeInfo inf = a.info[node];
+    const T ci = HAS_C ? Cp[p] : T(1);
+
+    Acc3<T, KAHAN> acc;
+    acc.zero();
+    bool slow = (ui.w < T(0)) || (inf.cut >= 0);
+    if (!slow) {
+        bool flag = false;
+        fast_loop<T, KAHAN, HAS_C>(a, src, Cp, lb1, ui, ci, a.thr[sm], acc, flag);
+        slow = flag;
+    }
+    bool dirty = false;
+    if (slow) {
+        acc.zero();
+        const uint4 cm = inf.cut >= 0 ? a.cut[inf.cut] : make_uint4(0, 0, 0, 0);
+        T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
+        hist_loop<T, KAHAN, HAS_C>(a, src, S0, Cp, Hs, lb1, node, ui, S0[p], ci, cm, acc, dirty);
+    }
+    if (a.force_only) {
+        double *L = a.L_out + 3 * sm;
+        L[0] = a.LV * ((double)acc.x - (KAHAN ? (double)acc.cx : 0.0));
+        L[1] = a.LV * ((double)acc.y - (KAHAN ? (double)acc.cy : 0.0));
+        L[2] = a.LV * ((double)acc.z - (KAHAN ? (double)acc.cz : 0.0));
+        return;
+    }
+    V4 vh = a.vh[sm];
+    V4 un = ui;
+    V4 cu, cvh;
+    if constexpr (KAHAN) {
+        cu = a.cu[sm];
+        cvh = a.cvh[sm];
+    } else {
+        cu = V4{};
+        cvh = V4{};
+    }
+    kick_drift<T, KAHAN>(a, acc.gx(), vh.x, cvh.x, un.x, cu.x);
+    kick_drift<T, KAHAN>(a, acc.gy(), vh.y, cvh.y, un.y, cu.y);
+    if (inf.bc == -1) {
+        kick_drift<T, KAHAN>(a, acc.gz(), vh.z, cvh.z, un.z, cu.z);
+    } else if (inf.bc == -2) {
+        vh.z = a.vload;
+        un.z = (T)(-(double)(n + 2) * a.du_s);
+        cu.z = T(0);
+        cvh.z = T(0);
+    } else {
+        vh.z = T(0);
+        un.z = T(0);
+        cu.z = T(0);
+        cvh.z = T(0);
+        a.rf[(int64_t)(n & 1) * a.rf_stride + (int64_t)sample * a.nsup + inf.bc] =
+            (double)acc.z - (KAHAN ? (double)acc.cz : 0.0);
+    }
+    un.w = dirty ? T(-1) : T(1);
+    a.u_next[(int64_t)sample * a.P + p] = un;
+    a.vh[sm] = vh;
+    if constexpr (KAHAN) {
+        a.cu[sm] = cu;
+        a.cvh[sm] = cvh;
+    }
+}
+
+// One time step for every (sample, tile) work item.
+//   LDS = false: a tile is kBlock consecutive nodes; neighbours come from the
+//                padded grid through the caches.
+//   LDS = true : a tile is a kBX x kBY x kBZ brick; the block first copies the
+//                brick and its kHalo-wide halo into LDS, then reads every
+//                neighbour from there.
+// Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8); each
+// XCD is given a contiguous range of work items so the halo a tile shares with
+// its neighbours stays in that XCD's L2.  The grid is padded to a multiple of
+// 8 and surplus blocks exit.
+template <typename T, bool KAHAN, bool HAS_C, bool LDS>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepParams<T> a)
+{
+    using V4 = typename Vec4<T>::t;
+    __shared__ V4 tile[LDS ? kTileN : 1];
+    const int64_t per_xcd = gridDim.x / kXcds;
+    const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (item >= a.n_items) return;
+    const int sample = (int)(item / a.tiles);
+    const int64_t t = item % a.tiles;
+    const int64_t n = a.step_base[sample] + a.k_local;
+    if (!a.force_only && t == 0 && n >= 1 && n <= a.n_steps) reduce_previous(a, sample, n);
+    if (!a.force_only && n >= a.n_steps) return;   // whole block: finished sample
+    const V4 *__restrict__ U = a.u_cur + (int64_t)sample * a.P;
+    if constexpr (LDS) {
+        const int bx = (int)(t % a.nbx), by = (int)((t / a.nbx) % a.nby), bz = (int)(t / ((int64_t)a.nbx * a.nby));
+        // the tile's first padded cell is the brick origin (node + kHalo - kHalo)
+        const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+        for (int q = threadIdx.x; q < kTileN; q += kBlock) {
+            const int lx = q % kLX, ly = (q / kLX) % kLY, lz = q / kLXY;
+            const int px = x0 + lx, py = y0 + ly, pz = z0 + lz;
+            V4 v{};
+            if (px < a.PX && py < a.PY && pz < a.PZ) v = U[px + (int64_t)py * a.PX + (int64_t)pz * a.PXY];
+            tile[q] = v;
+        }
+        __syncthreads();
+        const int tx = threadIdx.x % kBX, ty = (threadIdx.x / kBX) % kBY, tz = threadIdx.x / (kBX * kBY);
+        const int ix = x0 + tx, iy = y0 + ty, iz = z0 + tz;
+        if (ix >= a.nx || iy >= a.ny || iz >= a.nz) return;
+        const int64_t node = ix + (int64_t)a.nx * (iy + (int64_t)a.ny * iz);
+        const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
+        const int c = (tx + kHalo) + kLX * (ty + kHalo) + kLXY * (tz + kHalo);
+        const LdsSrc<T> src{tile, c};
+        node_step<T, KAHAN, HAS_C>(a, src, sample, n, node, p, tile[c]);
+    } else {
+        const int64_t node = t * kBlock + threadIdx.x;
+        if (node >= a.M) return;
+        const uint32_t nd = (uint32_t)node, nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+        const uint32_t r = nd / nx;
+        const int ix = (int)(nd - r * nx);
+        const int iz = (int)(r / ny);
+        const int iy = (int)(r - (uint32_t)iz * ny);
+        const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
+        const GlobalSrc<T> src{U, (uint32_t)p * (uint32_t)sizeof(V4), a.PX, a.PXY};
+        node_step<T, KAHAN, HAS_C>(a, src, sample, n, node, p, U[p]);
+    }
+}
+
+// Moves every sample's chunk base past the steps of one replayed chunk.
+static __global__ void advance_kernel(int64_t *step_base, int64_t S, int64_t by)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < S) step_base[g] += by;
+}
+
+}  // namespace pdmi

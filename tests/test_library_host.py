@@ -1,0 +1,101 @@
+"""CPU checks of libpdmi.so: it loads, exports every entry point declared in
+include/pd.h, and its host-side lattice, notch cut and pads agree exactly with
+the oracle's.  No compute call is made (there is no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G
+from paper_2212_04415_amd import pd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pd.h")).read()
+    return sorted(set(re.findall(r"PD_API\s+[\w\s\*]+?\b(pd_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pd.lib()
+    names = declared_symbols()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pd.SIGNATURES)
+
+
+def build(beam, dx, m_ratio=W.M_RATIO):
+    desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, beam.thickness, beam.depth), dx, m_ratio,
+                           beam.span, beam.notch_depth, beam.pad_width)
+    h = C.c_void_p()
+    rc = pd.lib().pd_build_mesh(C.byref(desc), C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("ell", [0, 1])
+def test_host_geometry_matches_oracle(ell):
+    lv = W.level(ell)
+    rc, h = build(lv.beam, lv.dx)
+    assert rc == 0, pd.pd_last_error()
+    try:
+        nb = C.c_int64()
+        assert pd.lib().pd_build_bonds(h, C.byref(nb)) == 0, pd.pd_last_error()
+        info = pd.pd_mesh_info_t()
+        pd.pd_mesh_get_info(h, C.byref(info))
+        shape = lv.shape
+        bi, bj, _ = G.unique_bonds(shape, W.M_RATIO)
+        cut = G.notch_cut_mask(shape, lv.dx, bi, bj, 0.5 * lv.beam.length, lv.beam.notch_depth)
+        assert (info.nx, info.ny, info.nz) == shape
+        assert info.n_nodes == np.prod(shape)
+        assert nb.value == info.n_bonds == bi.size - cut.sum()
+        assert info.n_cut == cut.sum()
+        assert info.n_stencil == 122
+        sup = np.zeros(info.n_support, dtype=np.int32)
+        ld = np.zeros(info.n_load, dtype=np.int32)
+        pd.pd_mesh_get_pads(h, sup.ctypes.data, ld.ctypes.data)
+        osup, old = G.beam_pads(shape, lv.dx, lv.beam)
+        assert np.array_equal(np.sort(sup), osup) and np.array_equal(np.sort(ld), old)
+    finally:
+        pd.pd_free_mesh(h)
+
+
+def test_host_geometry_size_sweep_beam():
+    beam = W.Beam.similar(100e-3)
+    rc, h = build(beam, 2.5e-3)
+    assert rc == 0, pd.pd_last_error()
+    try:
+        nb = C.c_int64()
+        pd.pd_build_bonds(h, C.byref(nb))
+        shape = G.grid_shape((beam.length, beam.thickness, beam.depth), 2.5e-3)
+        bi, bj, _ = G.unique_bonds(shape, W.M_RATIO)
+        cut = G.notch_cut_mask(shape, 2.5e-3, bi, bj, 0.5 * beam.length, beam.notch_depth)
+        assert nb.value == bi.size - cut.sum()
+    finally:
+        pd.pd_free_mesh(h)
+
+
+@pytest.mark.parametrize("bad", ["extent", "m_ratio", "pad_face", "notch"])
+def test_host_rejects_bad_geometry(bad):
+    beam, dx, m = W.Beam(), 5e-3, W.M_RATIO
+    if bad == "extent":
+        beam = W.Beam(length=176e-3)
+    elif bad == "m_ratio":
+        m = 2.5
+    elif bad == "pad_face":
+        beam = W.Beam(pad_width=10e-3, span=145e-3)      # pad faces through node centres
+    elif bad == "notch":
+        beam = W.Beam(notch_depth=3.3e-3)
+    rc, h = build(beam, dx, m)
+    assert rc == pd.PD_EINVAL
+    assert pd.pd_last_error()
+
+
+def test_null_arguments_are_rejected():
+    assert pd.lib().pd_build_mesh(None, None) == pd.PD_EINVAL
+    assert pd.lib().pd_run(None, None, None, None) == pd.PD_EINVAL
+    assert pd.lib().pd_level_stats(None, None, 0, None, None) == pd.PD_EINVAL
