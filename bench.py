@@ -39,12 +39,12 @@ FLOPS_PER_BOND_DIR_F64 = 32          # no compensation
 # used, so 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s.
 PEAK_TFLOPS_F32 = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_TFLOPS_F64 = 78.6
-STEP_KERNEL_F32 = "step_kernel<float, true, false>"
+STEP_KERNEL_F32 = "step_kernel<float, true, false, true>"
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("solver.hip", "pd_internal.h"):
+    for f in ("step_kernels.h", "pd_internal.h"):
         with open(os.path.join(ROOT, "paper_2212_04415_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
