@@ -238,3 +238,221 @@ int pdo_run(const pdo_problem *p, const double *u_init, const double *v_init,
     free(u); free(v); free(L); free(kappa); free(c_b); free(s0_b); free(sc_b); free(fixed_z);
     return 0;
 }
+
+/* ---------------------------------------------------------------- adjoint */
+
+/* keep = 1 - d as a function of (kappa, s0, sc), with its partial
+ * derivatives.  Outside (s0, sc) keep is constant (1 or 0) and every
+ * derivative is zero. */
+static void keep_derivs(int32_t law, double kappa, double s0, double sc, double k, double alpha,
+                        double *keep, double *dk, double *ds0, double *dsc)
+{
+    *dk = *ds0 = *dsc = 0.0;
+    if (!(kappa > s0)) { *keep = 1.0; return; }
+    if (kappa >= sc) { *keep = 0.0; return; }
+    double w = sc - s0;
+    double t = (kappa - s0) / w;
+    double t_k = 1.0 / w, t_s0 = (kappa - sc) / (w * w), t_sc = -(kappa - s0) / (w * w);
+    double g, g_t, g_s0;   /* keep = g / kappa with g = g(t, s0) */
+    if (law == PDO_LAW_EXPLIN) {
+        double ek = 1.0 - exp(-k);
+        double br = 1.0 - (1.0 - exp(-k * t)) / ek + alpha * (1.0 - t);
+        double br_t = -k * exp(-k * t) / ek - alpha;
+        g = s0 * br / (1.0 + alpha);
+        g_t = s0 * br_t / (1.0 + alpha);
+        g_s0 = br / (1.0 + alpha);
+    } else if (t <= 0.2) {
+        g = s0 * (1.0 - 4.0 * t);
+        g_t = -4.0 * s0;
+        g_s0 = 1.0 - 4.0 * t;
+    } else {
+        g = 0.25 * s0 * (1.0 - t);
+        g_t = -0.25 * s0;
+        g_s0 = 0.25 * (1.0 - t);
+    }
+    *keep = g / kappa;
+    *dk = g_t * t_k / kappa - g / (kappa * kappa);
+    *ds0 = (g_s0 + g_t * t_s0) / kappa;
+    *dsc = g_t * t_sc / kappa;
+}
+
+/* exposed for tests */
+void pdo_keep_derivs(int32_t law, double kappa, double s0, double sc, double k, double alpha, double *out4)
+{
+    keep_derivs(law, kappa, s0, sc, k, alpha, out4, out4 + 1, out4 + 2, out4 + 3);
+}
+
+/* Gradient of the peak reaction Q = R^{n*} (n* fixed by the forward run)
+ * with respect to the per-node limit-stretch field s0 and micromodulus field
+ * c, by the discrete adjoint of pdo_run's loop.  The forward pass keeps every
+ * displacement u^n and, for the damage history, the list of bonds whose
+ * largest stretch grew past their limit stretch at each step (with the old
+ * value), so the reverse sweep can restore kappa^n exactly.  Written with the
+ * half-step velocity w^n = v^n + (dt/2rho)(L^n - damping v^n) as the state:
+ *   w^n = A D w^{n-1} + h (1 + A D) L^n,  u^{n+1} = u^n + dt w^n  (free DOFs),
+ *   h = dt / 2rho, A = 1 - damping h, D = 1 / (1 + damping h),
+ *   kappa^n = max(kappa^{n-1}, s(u^n)),  L^n = F(u^n, kappa^n; s0, c),
+ *   R^n = -V sum_supports L^n_z.
+ * Starts from rest.  dQ_ds0 / dQ_dc: [n_nodes], overwritten. */
+int pdo_adjoint(const pdo_problem *p, double *Q_out, int64_t *nstar_out, double *dQ_ds0, double *dQ_dc)
+{
+    int64_t M = p->n_nodes, nb = p->n_bonds, N = p->n_steps;
+    double V = p->volume, h = p->dt / (2.0 * p->rho);
+    double A = 1.0 - p->damping * h, D = 1.0 / (1.0 + p->damping * h);
+    double a1 = A * D, a2 = h * (1.0 + A * D);
+    double *U = malloc(sizeof(double) * 3 * M * (N + 1));   /* u^0 .. u^N */
+    double *v = calloc(3 * M, sizeof(double)), *L = calloc(3 * M, sizeof(double));
+    double *kappa = malloc(sizeof(double) * nb);
+    double *c_b = malloc(sizeof(double) * nb), *s0_b = malloc(sizeof(double) * nb),
+           *sc_b = malloc(sizeof(double) * nb);
+    unsigned char *fixed_z = calloc(M, 1);
+    int64_t *ev_start = calloc(N + 2, sizeof(int64_t));
+    int64_t ev_cap = 1 << 16, ev_n = 0;
+    int32_t *ev_bond = malloc(sizeof(int32_t) * ev_cap);
+    double *ev_old = malloc(sizeof(double) * ev_cap);
+    if (!U || !v || !L || !kappa || !c_b || !s0_b || !sc_b || !fixed_z || !ev_start || !ev_bond || !ev_old)
+        return -2;
+    bond_params(p, c_b, s0_b, sc_b);
+    for (int64_t b = 0; b < nb; ++b) kappa[b] = -INFINITY;
+    for (int64_t a = 0; a < p->n_support; ++a) fixed_z[p->support[a]] = 1;
+    for (int64_t a = 0; a < p->n_load; ++a) fixed_z[p->load[a]] = 1;
+    memset(U, 0, sizeof(double) * 3 * M);
+
+    /* forward (same arithmetic as pdo_run) */
+    double Q = -INFINITY;
+    int64_t nstar = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        double *u0 = U + 3 * M * n, *u1 = U + 3 * M * (n + 1);
+        for (int64_t i = 0; i < M; ++i)
+            for (int d = 0; d < 3; ++d) {
+                if (d == 2 && fixed_z[i]) continue;
+                v[3 * i + d] += h * (L[3 * i + d] - p->damping * v[3 * i + d]);
+            }
+        for (int64_t i = 0; i < 3 * M; ++i) u1[i] = u0[i] + p->dt * v[i];
+        for (int64_t a = 0; a < p->n_support; ++a) {
+            u1[3 * p->support[a] + 2] = 0.0;
+            v[3 * p->support[a] + 2] = 0.0;
+        }
+        for (int64_t a = 0; a < p->n_load; ++a) {
+            u1[3 * p->load[a] + 2] = p->load_offset - (double)(n + 1) * p->du;
+            v[3 * p->load[a] + 2] = -p->du / p->dt;
+        }
+        /* damage history events of step n+1 */
+        ev_start[n + 1] = ev_n;
+        for (int64_t b = 0; b < nb; ++b) {
+            int32_t i = p->bond_i[b], j = p->bond_j[b];
+            const double *xi = p->xi + 3 * b;
+            double y[3];
+            for (int d = 0; d < 3; ++d) y[d] = xi[d] + (u1[3 * j + d] - u1[3 * i + d]);
+            double ylen = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+            double xlen = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+            double s = (ylen - xlen) / xlen;
+            if (s > kappa[b] && s > s0_b[b]) {
+                if (ev_n == ev_cap) {
+                    ev_cap *= 2;
+                    ev_bond = realloc(ev_bond, sizeof(int32_t) * ev_cap);
+                    ev_old = realloc(ev_old, sizeof(double) * ev_cap);
+                    if (!ev_bond || !ev_old) return -2;
+                }
+                ev_bond[ev_n] = (int32_t)b;
+                ev_old[ev_n] = kappa[b];
+                ++ev_n;
+            }
+        }
+        force_eval(p, u1, kappa, c_b, s0_b, sc_b, L);
+        for (int64_t i = 0; i < M; ++i)
+            for (int d = 0; d < 3; ++d) {
+                if (d == 2 && fixed_z[i]) continue;
+                v[3 * i + d] = (v[3 * i + d] + h * L[3 * i + d]) / (1.0 + p->damping * h);
+            }
+        double R = 0.0;
+        for (int64_t a = 0; a < p->n_support; ++a) R -= L[3 * p->support[a] + 2] * V;
+        if (R > Q) { Q = R; nstar = n + 1; }
+    }
+    ev_start[N + 1] = ev_n;
+    *Q_out = Q;
+    if (nstar_out) *nstar_out = nstar;
+
+    /* kappa^{n*}: undo the growth events of steps after n* */
+    for (int64_t m = N; m > nstar; --m)
+        for (int64_t e = ev_start[m + 1] - 1; e >= ev_start[m]; --e) kappa[ev_bond[e]] = ev_old[e];
+
+    /* reverse sweep */
+    double *ub_next = calloc(3 * M, sizeof(double)), *ub = calloc(3 * M, sizeof(double));
+    double *wb = calloc(3 * M, sizeof(double)), *Lb = calloc(3 * M, sizeof(double));
+    double *kb = calloc(nb, sizeof(double));
+    unsigned char *active = calloc(nb, 1);
+    if (!ub_next || !ub || !wb || !Lb || !kb || !active) return -2;
+    memset(dQ_ds0, 0, sizeof(double) * M);
+    memset(dQ_dc, 0, sizeof(double) * M);
+    for (int64_t m = nstar; m >= 1; --m) {
+        const double *um = U + 3 * M * m;
+        /* u^{m+1} = u^m + dt w^m on free DOFs */
+        for (int64_t i = 0; i < M; ++i)
+            for (int d = 0; d < 3; ++d) {
+                int64_t q = 3 * i + d;
+                double g = (d == 2 && fixed_z[i]) ? 0.0 : ub_next[q];
+                wb[q] = (d == 2 && fixed_z[i]) ? 0.0 : wb[q] + p->dt * g;
+                ub[q] = g;
+                Lb[q] = a2 * wb[q];
+            }
+        if (m == nstar)
+            for (int64_t a = 0; a < p->n_support; ++a) Lb[3 * p->support[a] + 2] += -V;
+        /* L^m = F(u^m, kappa^m) */
+        for (int64_t e = ev_start[m]; e < ev_start[m + 1]; ++e) active[ev_bond[e]] = 1;
+        for (int64_t b = 0; b < nb; ++b) {
+            int32_t i = p->bond_i[b], j = p->bond_j[b];
+            const double *xi = p->xi + 3 * b;
+            double y[3], Fb[3];
+            for (int d = 0; d < 3; ++d) y[d] = xi[d] + (um[3 * j + d] - um[3 * i + d]);
+            double l = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+            double x0 = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+            double s = (l - x0) / x0;
+            double yh[3] = {y[0] / l, y[1] / l, y[2] / l};
+            for (int d = 0; d < 3; ++d) Fb[d] = Lb[3 * i + d] - Lb[3 * j + d];
+            double proj = yh[0] * Fb[0] + yh[1] * Fb[1] + yh[2] * Fb[2];
+            double keep, dk, ds0, dsc;
+            keep_derivs(p->law, kappa[b], s0_b[b], sc_b[b], p->k, p->alpha, &keep, &dk, &ds0, &dsc);
+            double cb = c_b[b];
+            /* y-bar = V c keep [yh proj / |xi| + (s / l)(F - yh proj)] */
+            double ybar[3];
+            for (int d = 0; d < 3; ++d)
+                ybar[d] = V * cb * keep * (yh[d] * proj / x0 + (s / l) * (Fb[d] - yh[d] * proj));
+            /* damage history: F depends on kappa through keep */
+            kb[b] += V * cb * s * dk * proj;
+            /* fields: sc = s0 + G / (c s0), G from the fracture-energy relation */
+            double Gm = (sc_b[b] - s0_b[b]) * cb * s0_b[b];
+            double dsc_dc = -Gm / (cb * cb * s0_b[b]);
+            double dsc_ds0 = 1.0 - Gm / (cb * s0_b[b] * s0_b[b]);
+            double cbar = V * s * proj * (keep + cb * dsc * dsc_dc);
+            double s0bar = V * cb * s * proj * (ds0 + dsc * dsc_ds0);
+            dQ_dc[i] += 0.5 * cbar;
+            dQ_dc[j] += 0.5 * cbar;
+            dQ_ds0[i] += 0.5 * s0bar;
+            dQ_ds0[j] += 0.5 * s0bar;
+            /* kappa^m = max(kappa^{m-1}, s(u^m)) */
+            if (active[b]) {
+                for (int d = 0; d < 3; ++d) ybar[d] += kb[b] * yh[d] / x0;
+                kb[b] = 0.0;
+            }
+            for (int d = 0; d < 3; ++d) {
+                ub[3 * j + d] += ybar[d];
+                ub[3 * i + d] -= ybar[d];
+            }
+        }
+        /* restore kappa^{m-1} and clear the active marks */
+        for (int64_t e = ev_start[m + 1] - 1; e >= ev_start[m]; --e) {
+            kappa[ev_bond[e]] = ev_old[e];
+            active[ev_bond[e]] = 0;
+        }
+        /* w^m = a1 w^{m-1} + a2 L^m */
+        for (int64_t q = 0; q < 3 * M; ++q) {
+            wb[q] *= a1;
+            ub_next[q] = ub[q];
+        }
+    }
+    free(U); free(v); free(L); free(kappa); free(c_b); free(s0_b); free(sc_b); free(fixed_z);
+    free(ev_start); free(ev_bond); free(ev_old);
+    free(ub_next); free(ub); free(wb); free(Lb); free(kb); free(active);
+    return 0;
+}

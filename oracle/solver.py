@@ -72,6 +72,10 @@ def lib():
         L.pdo_force.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
         L.pdo_stretch.restype = C.c_int
         L.pdo_stretch.argtypes = [P, C.c_void_p, C.c_void_p]
+        L.pdo_keep_derivs.restype = None
+        L.pdo_keep_derivs.argtypes = [C.c_int32, d, d, d, d, d, C.c_void_p]
+        L.pdo_adjoint.restype = C.c_int
+        L.pdo_adjoint.argtypes = [P, C.POINTER(d), C.POINTER(i64), C.c_void_p, C.c_void_p]
         L.pdo_run.restype = C.c_int
         L.pdo_run.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(d), C.POINTER(i64),
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -90,6 +94,13 @@ def critical_stretch(law, s0, c, GF, delta, k, alpha):
 
 def damage(law, kappa, s0, sc, k, alpha):
     return lib().pdo_damage(law, kappa, s0, sc, k, alpha)
+
+
+def keep_derivs(law, kappa, s0, sc, k, alpha):
+    """(keep, d/dkappa, d/ds0, d/dsc) of keep = 1 - damage."""
+    out = np.zeros(4)
+    lib().pdo_keep_derivs(law, kappa, s0, sc, k, alpha, out.ctypes.data)
+    return out
 
 
 def _ptr(a):
@@ -160,6 +171,16 @@ class Problem:
         st = self._struct()
         lib().pdo_stretch(C.byref(st), _ptr(u), _ptr(s))
         return s
+
+    def adjoint(self):
+        """Peak reaction, its step and dQ/ds0, dQ/dc per node (discrete
+        adjoint of run(); starts from rest)."""
+        Q = C.c_double(0.0); ns = C.c_int64(0)
+        g0 = np.zeros(self.n_nodes); gc = np.zeros(self.n_nodes)
+        st = self._struct()
+        rc = lib().pdo_adjoint(C.byref(st), C.byref(Q), C.byref(ns), _ptr(g0), _ptr(gc))
+        assert rc == 0, rc
+        return dict(Q=Q.value, nstar=ns.value, dQ_ds0=g0, dQ_dc=gc)
 
     def run(self, u_init=None, v_init=None, kappa_init=None, want_state=True):
         """Returns dict(Q, nstar, R, u, v, kappa)."""
