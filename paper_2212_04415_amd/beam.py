@@ -192,3 +192,20 @@ def level_stats(q_fine, q_coarse=None, stream=None):
     pd.pd_level_stats(q_fine.data_ptr(), q_coarse.data_ptr() if q_coarse is not None else None,
                       q_fine.numel(), sums.data_ptr(), _stream_ptr(stream))
     return sums
+
+
+def qoi_grad(mesh: Mesh, params, s0=None, c=None, stream=None):
+    """Peak reaction, its step, and dQ/ds0, dQ/dc per node (pd_qoi_grad).
+    s0 / c: per-node fields (array-like, FP64) or None for homogeneous."""
+    import torch
+    dev = torch.device("cuda")
+    s0_t = None if s0 is None else torch.as_tensor(np.asarray(s0, dtype=np.float64), device=dev).contiguous()
+    c_t = None if c is None else torch.as_tensor(np.asarray(c, dtype=np.float64), device=dev).contiguous()
+    g0 = torch.empty(mesh.n_nodes, dtype=torch.float64, device=dev)
+    gc = torch.empty(mesh.n_nodes, dtype=torch.float64, device=dev)
+    Q = C.c_double()
+    ns = C.c_int64()
+    pd.pd_qoi_grad(mesh.h, C.byref(params), s0_t.data_ptr() if s0_t is not None else None,
+                   c_t.data_ptr() if c_t is not None else None, g0.data_ptr(), gc.data_ptr(),
+                   C.byref(Q), C.byref(ns), _stream_ptr(stream))
+    return dict(Q=Q.value, nstar=ns.value, dQ_ds0=g0.cpu().numpy(), dQ_dc=gc.cpu().numpy())

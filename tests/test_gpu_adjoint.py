@@ -1,0 +1,98 @@
+"""GPU adjoint (pd_qoi_grad) against the oracle's adjoint and against
+central finite differences of the GPU forward solve."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G
+from oracle import kl as OKL
+from oracle import solver as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2212_04415_amd import beam
+    return beam
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("law", [W.LAW_EXPLIN, W.LAW_TRILINEAR])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint_matches_oracle_level0(B, law, precision):
+    """Level-0 beam, cracking load, random s0 and c fields, 1000 steps with a
+    checkpoint every 96 steps (the last segment is ragged)."""
+    lv = W.level(0, fracture=True, law=law)
+    rng = np.random.default_rng(12)
+    M = int(np.prod(lv.shape))
+    s0 = W.S0_MEAN * np.exp(0.1 * rng.standard_normal(M))
+    prob = S.beam_problem(lv, s0=s0, du=4e-8, n_steps=1000)
+    c = prob.c * np.exp(0.05 * rng.standard_normal(M))
+    prob.c = c
+    ref = prob.adjoint()
+    mesh = B.Mesh.for_level(lv)
+    p = B.make_params(lv, precision=precision, du=4e-8, n_steps=1000, checkpoint_every=96)
+    out = B.qoi_grad(mesh, p, s0, c)
+    tol = 1e-6 if precision == "f64" else 5e-2
+    assert out["Q"] == pytest.approx(ref["Q"], rel=1e-9 if precision == "f64" else 5e-3)
+    assert out["nstar"] == ref["nstar"] or precision == "f32"
+    if out["nstar"] == ref["nstar"]:
+        e0, ec = rel_l2(out["dQ_ds0"], ref["dQ_ds0"]), rel_l2(out["dQ_dc"], ref["dQ_dc"])
+        print(f"rel L2: ds0 {e0:.2e}, dc {ec:.2e}")
+        assert e0 < tol and ec < tol
+
+
+def test_adjoint_elastic_limit_stretch_gradient_is_zero(B):
+    lv = W.level(0)
+    mesh = B.Mesh.for_level(lv)
+    out = B.qoi_grad(mesh, B.make_params(lv, precision="f64", n_steps=500, checkpoint_every=64))
+    assert np.all(out["dQ_ds0"] == 0.0)
+    assert np.abs(out["dQ_dc"]).max() > 0
+
+
+@pytest.mark.slow
+def test_adjoint_level1_against_finite_differences(B):
+    """The level-1 adjoint workload: 28,000 nodes, one KL field sample (seed 3),
+    cracking load, 8000 steps, checkpoint every 200, FP64; central finite
+    differences (h = 1e-4 relative) of the same GPU forward solve along a
+    random direction and on 20 random nodes (10 in the cracking zone)."""
+    lv = W.level(1, fracture=True, law=W.LAW_EXPLIN)
+    mesh = B.Mesh.for_level(lv)
+    ob = OKL.Basis3D((lv.beam.length, lv.beam.thickness, lv.beam.depth), W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    pos = G.node_positions(mesh.shape, lv.dx)
+    s0 = OKL.lognormal_field(ob, pos, W.kl_coefficients(3, 1), W.S0_MEAN, W.FIELD_COV)[0]
+    p = B.make_params(lv, precision="f64", checkpoint_every=200)
+    out = B.qoi_grad(mesh, p, s0)
+    g = out["dQ_ds0"]
+    h = 1e-4
+
+    def peak(field):
+        mesh.set_field(0, field)
+        return B.run(mesh, p)["Q"]
+
+    rng = np.random.default_rng(3)
+    dirn = rng.standard_normal(mesh.n_nodes)
+    fd = (peak(s0 * (1 + h * dirn)) - peak(s0 * (1 - h * dirn))) / 2
+    ad = np.dot(g, h * s0 * dirn)
+    print(f"directional: fd {fd:.6e} adjoint {ad:.6e}")
+    assert ad == pytest.approx(fd, rel=2e-2)
+    zone = np.argsort(-np.abs(g))[:200]
+    picks = list(rng.choice(zone, 10, replace=False)) + list(rng.choice(mesh.n_nodes, 10, replace=False))
+    ok = 0
+    for i in picks:
+        e = np.zeros(mesh.n_nodes)
+        e[i] = h * s0[i]
+        fdi = (peak(s0 + e) - peak(s0 - e)) / 2
+        adi = g[i] * h * s0[i]
+        good = abs(fdi - adi) <= 2e-2 * max(abs(fdi), 1e-3 * abs(fd)) + 1e-9
+        print(f"node {i}: fd {fdi:.4e} adjoint {adi:.4e} {'ok' if good else 'differs'}")
+        ok += good
+    mesh.set_field(0, None)
+    assert ok >= 16
