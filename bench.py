@@ -91,6 +91,25 @@ def cpu_baseline(seconds_target=15.0):
                       f"{dt:.1f} s, single-threaded C at -O2"}
 
 
+def mlmc_leg(fracture=True):
+    """The three-level MLMC batch (dx = 5 / 2.5 / 1.25 mm; 1024 / 128 / 16
+    samples, each level-l>0 sample paired with a coarse solve on the same KL
+    coefficients: 1152 / 144 / 16 solves) in one batched call."""
+    import workloads as W
+    from paper_2212_04415_amd import mlmc
+    levels = [W.level(l, fracture=fracture) for l in range(3)]
+    out = mlmc.coupled_batch(levels, [1024, 128, 16], seed=2, precision="f32", corr_len=W.FIELD_CORR_LEN,
+                             n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
+                             kl_coefficients=W.kl_coefficients)
+    bu = sum(b * n * st for b, n, st in zip(out["bonds"], out["solves"], out["steps"]))
+    return {"wall_s": out["wall_s"], "bond_updates_per_s": bu / out["wall_s"],
+            "mlmc_samples_per_s": (1024 + 128 + 16) / out["wall_s"],
+            "solves_per_level": out["solves"], "estimate_N": out["estimate"],
+            "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "level_mean_var": [[m, v] for m, v, _ in out["levels"]],
+            "load_per_step_mm_L0": levels[0].du * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +117,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain FP64 and cracking-load legs")
+    ap.add_argument("--mlmc", action="store_true",
+                    help="also run the three-level MLMC hierarchy (1024/128/16 samples + coupled partners)")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="profiling only: time steps per batch solve (default: the workload's 8000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -212,6 +233,9 @@ def main():
                                     "samples_per_s": S / dtf, "peak_mean_N": float(qf.mean()),
                                     "peak_cov": float(qf.std() / qf.mean()),
                                     "load_per_step_mm": lvf.du * 1e3}
+
+    if args.mlmc:
+        line["mlmc_hierarchy"] = mlmc_leg(fracture=True)
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

@@ -225,6 +225,14 @@ PD_API int pd_kl_free(pd_kl kl);
 PD_API int pd_level_stats(const double *q_fine_dev, const double *q_coarse_dev, int64_t n,
                    double *sums_dev, void *stream);
 
+/* MLMC estimate from the level sums of pd_level_stats (paper section 4:
+ * Eq. MC_estimator, Eq. sample_variance, Eq. MLMC_estimator, Eq. MLMC_error).
+ * sums_dev: device FP64 [n_levels][3] = (N_l, sum Y_l, sum Y_l^2), level 0
+ * first.  out_host: host FP64 [2 + 3 n_levels] = (estimate sum_l mean_l,
+ * sampling variance sum_l V_l / N_l, then per level: mean_l, V_l with 1/N,
+ * V_l with 1/(N-1)).  Synchronises stream. */
+PD_API int pd_mlmc_estimate(const double *sums_dev, int32_t n_levels, double *out_host, void *stream);
+
 PD_API int pd_free_mesh(pd_mesh m);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -209,3 +209,38 @@ def qoi_grad(mesh: Mesh, params, s0=None, c=None, stream=None):
                    c_t.data_ptr() if c_t is not None else None, g0.data_ptr(), gc.data_ptr(),
                    C.byref(Q), C.byref(ns), _stream_ptr(stream))
     return dict(Q=Q.value, nstar=ns.value, dQ_ds0=g0.cpu().numpy(), dQ_dc=gc.cpu().numpy())
+
+
+def mlmc_estimate(level_sums, stream=None):
+    """Estimator from per-level (N, sum Y, sum Y^2) device tensors, via
+    pd_mlmc_estimate.  Returns dict(estimate, sampling_variance, levels=[(mean,
+    var, var_unbiased), ...])."""
+    import torch
+    sums = torch.stack(list(level_sums)).contiguous()
+    L = sums.shape[0]
+    out = np.zeros(2 + 3 * L)
+    pd.pd_mlmc_estimate(sums.data_ptr(), L, out.ctypes.data, _stream_ptr(stream))
+    return dict(estimate=out[0], sampling_variance=out[1],
+                levels=[tuple(out[2 + 3 * l: 5 + 3 * l]) for l in range(L)])
+
+
+def peak_load_function():
+    """torch.autograd.Function: peak reaction of one sample as a function of
+    its per-node s0 and c fields (FP64 device tensors); backward applies the
+    hand-written adjoint (pd_qoi_grad)."""
+    import torch
+
+    class PeakLoad(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, s0, c, mesh, params):
+            out = qoi_grad(mesh, params, s0.detach().cpu().numpy(), c.detach().cpu().numpy())
+            ctx.save_for_backward(torch.as_tensor(out["dQ_ds0"], device=s0.device),
+                                  torch.as_tensor(out["dQ_dc"], device=c.device))
+            return torch.tensor(out["Q"], dtype=torch.float64, device=s0.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            gs0, gc = ctx.saved_tensors
+            return g * gs0, g * gc, None, None
+
+    return PeakLoad

@@ -150,4 +150,28 @@ int pd_level_stats(const double *q_fine_dev, const double *q_coarse_dev, int64_t
     return PD_OK;
 }
 
+int pd_mlmc_estimate(const double *sums_dev, int32_t n_levels, double *out_host, void *stream)
+{
+    if (!sums_dev || !out_host || n_levels < 1) return fail(PD_EINVAL, "bad arguments");
+    std::vector<double> sums(3 * (size_t)n_levels);
+    PD_HIP(hipMemcpyAsync(sums.data(), sums_dev, 8 * sums.size(), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    PD_HIP(hipStreamSynchronize((hipStream_t)stream));
+    double est = 0.0, var = 0.0;
+    for (int l = 0; l < n_levels; ++l) {
+        const double n = sums[3 * l], s1 = sums[3 * l + 1], s2 = sums[3 * l + 2];
+        if (!(n >= 1)) return fail(PD_EINVAL, "level %d has no samples", l);
+        const double mean = s1 / n;
+        const double v = s2 / n - mean * mean;                // Eq. sample_variance
+        const double vu = n > 1 ? v * n / (n - 1) : NAN;
+        out_host[2 + 3 * l] = mean;
+        out_host[3 + 3 * l] = v;
+        out_host[4 + 3 * l] = vu;
+        est += mean;                                          // Eq. MLMC_estimator
+        var += v / n;                                         // sampling error of Eq. MLMC_error
+    }
+    out_host[0] = est;
+    out_host[1] = var;
+    return PD_OK;
+}
+
 }  // extern "C"

@@ -72,6 +72,7 @@ SIGNATURES = {
     "pd_kl_field": [_vp, _vp, _i64, _d, _d, _vp, _i32, _vp],
     "pd_kl_free": [_vp],
     "pd_level_stats": [_vp, _vp, _i64, _vp, _vp],
+    "pd_mlmc_estimate": [_vp, _i32, _vp, _vp],
     "pd_free_mesh": [_vp],
     "pd_last_error": [],
 }
@@ -126,6 +127,7 @@ pd_kl_eigenvalues = _wrap("pd_kl_eigenvalues")
 pd_kl_field = _wrap("pd_kl_field")
 pd_kl_free = _wrap("pd_kl_free")
 pd_level_stats = _wrap("pd_level_stats")
+pd_mlmc_estimate = _wrap("pd_mlmc_estimate")
 pd_free_mesh = _wrap("pd_free_mesh")
 
 
