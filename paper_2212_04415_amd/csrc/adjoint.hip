@@ -245,22 +245,26 @@ static int qoi_grad(pd_mesh_s *m, const pd_params *p, const double *s0_dev, cons
     if ((rc = setup_solve<T>(s, s0_dev, m->M, c_dev, m->M, st))) return rc;
 
     const size_t ubytes = sizeof(V4) * m->P, vbytes = sizeof(V4) * m->M, hbytes = sizeof(T) * kStencil * m->M;
+    const size_t dbytes = sizeof(uint4) * m->M;
     const int64_t n_ck = (N + K - 1) / K;
     DevBuf mem;
-    std::vector<void *> ck_u(n_ck), ck_vh(n_ck), ck_cu(n_ck), ck_cvh(n_ck), ck_h(n_ck);
+    std::vector<void *> ck_u(n_ck), ck_vh(n_ck), ck_cu(n_ck), ck_cvh(n_ck), ck_h(n_ck), ck_d(n_ck);
     for (int64_t c = 0; c < n_ck; ++c) {
-        if ((rc = mem.get(&ck_u[c], ubytes)) || (rc = mem.get(&ck_vh[c], vbytes)) || (rc = mem.get(&ck_h[c], hbytes)))
+        if ((rc = mem.get(&ck_u[c], ubytes)) || (rc = mem.get(&ck_vh[c], vbytes)) || (rc = mem.get(&ck_h[c], hbytes)) ||
+            (rc = mem.get(&ck_d[c], dbytes)))
             return rc;
         if (kahan && ((rc = mem.get(&ck_cu[c], vbytes)) || (rc = mem.get(&ck_cvh[c], vbytes)))) return rc;
     }
     auto d2d = [&](void *dst, const void *src, size_t n) { return hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, st); };
     // forward with checkpoints: before launch k the state is (u^{k+1}, w^k, kappa^k)
+    // plus the damaged-bond bits of kappa^k
     for (int64_t k = 0; k < N; ++k) {
         if (k % K == 0) {
             const int64_t c = k / K;
             PD_HIP(d2d(ck_u[c], s.b.u[k & 1], ubytes));
             PD_HIP(d2d(ck_vh[c], s.b.vh, vbytes));
             PD_HIP(d2d(ck_h[c], s.b.hist, hbytes));
+            PD_HIP(d2d(ck_d[c], s.b.dmask, dbytes));
             if (kahan) {
                 PD_HIP(d2d(ck_cu[c], s.b.cu, vbytes));
                 PD_HIP(d2d(ck_cvh[c], s.b.cvh, vbytes));
@@ -335,6 +339,7 @@ static int qoi_grad(pd_mesh_s *m, const pd_params *p, const double *s0_dev, cons
         PD_HIP(d2d(s.b.u[k0 & 1], ck_u[c], ubytes));
         PD_HIP(d2d(s.b.vh, ck_vh[c], vbytes));
         PD_HIP(d2d(s.b.hist, ck_h[c], hbytes));
+        PD_HIP(d2d(s.b.dmask, ck_d[c], dbytes));
         if (kahan) {
             PD_HIP(d2d(s.b.cu, ck_cu[c], vbytes));
             PD_HIP(d2d(s.b.cvh, ck_cvh[c], vbytes));

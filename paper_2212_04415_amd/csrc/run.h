@@ -111,7 +111,7 @@ struct RunBuffers {
     bool f64 = false, kahan = true, has_c = false;
     void *u[2] = {nullptr, nullptr};
     void *vh = nullptr, *cu = nullptr, *cvh = nullptr;
-    void *hist = nullptr, *s0pad = nullptr, *thr = nullptr, *cpad = nullptr;
+    void *hist = nullptr, *dmask = nullptr, *s0pad = nullptr, *thr = nullptr, *cpad = nullptr;
     double *rf = nullptr, *Q = nullptr, *hist_R = nullptr;
     int64_t *nstar = nullptr, *step = nullptr;
     int32_t *status = nullptr;
@@ -149,6 +149,7 @@ static int alloc_run(const pd_mesh_s *m, int S, bool f64, bool kahan, bool has_c
         if ((rc = b.alloc(&b.cvh, v4 * m->M * S))) return rc;
     }
     if ((rc = b.alloc(&b.hist, ts * kStencil * m->M * S))) return rc;
+    if ((rc = b.alloc(&b.dmask, sizeof(uint4) * m->M * S))) return rc;
     if ((rc = b.alloc(&b.s0pad, ts * m->P * S))) return rc;
     if ((rc = b.alloc(&b.thr, ts * m->M * S))) return rc;
     if (has_c && (rc = b.alloc(&b.cpad, ts * m->P * S))) return rc;
@@ -194,6 +195,7 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     a.cu = (V4 *)b.cu;
     a.cvh = (V4 *)b.cvh;
     a.hist = (T *)b.hist;
+    a.dmask = (uint4 *)b.dmask;
     a.s0pad = (const T *)b.s0pad;
     a.thr = (const T *)b.thr;
     a.cpad = (const T *)b.cpad;
@@ -295,6 +297,7 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
     }
     int64_t nh = (int64_t)kStencil * m->M * S;
     fill_kernel<T><<<blocks_for(nh), 256, 0, st>>>((T *)s.b.hist, nh, T(0));
+    fill_kernel<uint32_t><<<blocks_for(4 * m->M * S), 256, 0, st>>>((uint32_t *)s.b.dmask, 4 * m->M * S, 0u);
     fields_kernel<T, In><<<nb, 256, 0, st>>>((T *)s.b.s0pad, (T *)s.b.cpad, s0, c, s.p.s0, 1.0 / s.mat.c_ref, m->P, m->M,
                                          S, m->nx, m->ny, m->nz, m->PX, (int64_t)m->PX * m->PY, s0_stride, c_stride);
     threshold_kernel<T><<<blocks_for(m->M * S), 256, 0, st>>>((T *)s.b.thr, (const T *)s.b.s0pad, m->P, m->M, S,

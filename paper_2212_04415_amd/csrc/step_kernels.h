@@ -11,12 +11,14 @@
 // Layout (per sample; all arrays sample-major):
 //   u     : padded grid of (u_x, u_y, u_z, flag) in units of dx, ping-pong.
 //           kHalo ghost layers per face hold flag 0; flag +1 marks a node
-//           whose bonds are all below their limit stretch, -1 a node with a
-//           damaged bond.  |flag| is the neighbour-existence weight.
+//           whose bonds have all stayed inside the plain fast path, -1 a node
+//           that has had a damaged, near-limit or strongly compressed bond.
+//           |flag| is the neighbour-existence weight.
 //   vh    : half-step velocity (dx/s); in FP32 also the compensation terms of
 //           vh and u;
-//   hist  : largest stretch of each bond direction, [122][M], touched only by
-//           nodes with a damaged bond (0 until the bond passes its limit);
+//   hist  : largest stretch of each bond direction, [122][M], touched only
+//           for damaged bonds (0 until the bond passes its limit);
+//   dmask : per node, one bit per bond direction that has passed its limit;
 //   s0pad : padded per-node limit stretch (+inf on ghosts); thr: per-node
 //           lower bound of the limit stretches of its bonds.
 #pragma once
@@ -74,6 +76,7 @@ struct StepParams {
     V4 *cu;             // FP32 only: compensation of u
     V4 *cvh;            // FP32 only: compensation of vh
     T *hist;            // [S][122][M]
+    uint4 *dmask;       // [S][M] damaged-bond bits, one per slot
     const T *s0pad;     // [S][P]
     const T *thr;       // [S][M]
     const T *cpad;      // [S][P] c / c_ref, or null
@@ -267,26 +270,35 @@ template <typename T> struct FastLoad {
 };
 
 // ---------------------------------------------------------------- fast path
-// All bonds of the node are known to be below their limit stretch (d = 0);
-// flag is raised when a bond may have reached the node's lower bound of limit
-// stretches (or is compressed beyond 2^-13), and the node is then redone on
-// the history path.
+// Every bond of the node is evaluated with compile-time offsets.
+//
+// Plain form (MASKED = false): all bonds of the node are known to be below
+// their limit stretch (d = 0); flag is raised when a bond may have reached the
+// node's lower bound of limit stretches (or is compressed beyond 2^-13), and
+// the node is then redone in masked form.
+//
+// Masked form: bonds listed in `skip` (notch-cut or damaged) and bonds that
+// reach the threshold or leave the series range contribute nothing here and
+// are returned in `exc` (a superset of `skip`) for the exception pass.
 //
 // In FP32 the stretch and the force weight w = s / |v + e| of an undamaged
 // bond are evaluated without square root or division: with x = num / (2|v|^2),
 // |v + e| = |v| sqrt(1 + 2x), so
 //   s = sqrt(1 + 2x) - 1 <= x,
-//   w = (1 - (1 + 2x)^(-1/2)) / |v| = (x / |v|)(1 - 3/2 x + 5/2 x^2 - ...).
-// On this path |x| < 2^-13 (larger tensions are flagged through s <= x,
-// larger compressions explicitly), so keeping two terms leaves a relative
-// error below 5/2 * 2^-26 = 3.7e-8, under FP32 rounding (2^-24 = 6e-8).  FP64
-// and the history path use the closed form.
+//   w = (1 - (1 + 2x)^(-1/2)) / |v| = (x / |v|)(1 - 3/2 x + 5/2 x^2 - 35/8 x^3 ...).
+// The plain form keeps two terms for |x| < 2^-13 (larger tensions are flagged
+// through s <= x, larger compressions explicitly): relative error below
+// 5/2 * 2^-26 = 3.7e-8, under FP32 rounding (2^-24 = 6e-8).  The masked form
+// keeps three terms for |x| < 2^-10: error below 35/8 * 2^-30 = 4.1e-9.  FP64
+// and the exception pass use the closed form.
 constexpr double kSeriesBound = 1.0 / 8192;
+constexpr double kSeriesBound3 = 1.0 / 1024;
 
-template <typename T, bool KAHAN, bool HAS_C, typename Src>
+template <typename T, bool KAHAN, bool HAS_C, bool MASKED, typename Src>
 __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src, const T *__restrict__ Cp,
                                           uint32_t lb1, const typename Vec4<T>::t &ui, T ci, T thr,
-                                          Acc3<T, KAHAN> &acc, bool &flag)
+                                          Acc3<T, KAHAN> &acc, bool &flag, const uint32_t (&skip)[4],
+                                          uint32_t (&exc)[4])
 {
     auto load = [&](auto kc) {
         constexpr Off v = kHalf.v[decltype(kc)::value];
@@ -311,22 +323,47 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         T eax, eay, eaz, ebx, eby, ebz, wa, wb;
         const T na = num_c<T, v.x, v.y, v.z, 1>(ui, r.a, eax, eay, eaz);
         const T nb = num_c<T, v.x, v.y, v.z, -1>(ui, r.b, ebx, eby, ebz);
+        bool exa = false, exb = false;
         if constexpr (sizeof(T) == 4) {
             const T xa = na * T(0.5 / V2), xb = nb * T(0.5 / V2);
             const T xwa = xa * fabs(r.a.w), xwb = xb * fabs(r.b.w);
-            hi = fmax(hi, fmax(xwa, xwb));
-            lo = fmin(lo, fmin(xwa, xwb));
             constexpr T IV = T(1.0 / kSqrtInt[V2]);
             constexpr T IV15 = T(-1.5 / kSqrtInt[V2]);
-            wa = xwa * fma_(xa, IV15, IV);
-            wb = xwb * fma_(xb, IV15, IV);
+            if constexpr (MASKED) {
+                constexpr T IV25 = T(2.5 / kSqrtInt[V2]);
+                exa = (xwa > thr) || (xwa < T(-kSeriesBound3));
+                exb = (xwb > thr) || (xwb < T(-kSeriesBound3));
+                wa = xwa * fma_(xa, fma_(xa, IV25, IV15), IV);
+                wb = xwb * fma_(xb, fma_(xb, IV25, IV15), IV);
+            } else {
+                hi = fmax(hi, fmax(xwa, xwb));
+                lo = fmin(lo, fmin(xwa, xwb));
+                wa = xwa * fma_(xa, IV15, IV);
+                wb = xwb * fma_(xb, IV15, IV);
+            }
         } else {
             T rya, ryb;
             const T sa = stretch_from_num(na, T(V2), T(kSqrtInt[V2]), rya) * fabs(r.a.w);
             const T sb = stretch_from_num(nb, T(V2), T(kSqrtInt[V2]), ryb) * fabs(r.b.w);
-            hi = fmax(hi, fmax(sa, sb));
+            if constexpr (MASKED) {
+                exa = sa > thr;
+                exb = sb > thr;
+            } else {
+                hi = fmax(hi, fmax(sa, sb));
+            }
             wa = sa * rya;
             wb = sb * ryb;
+        }
+        if constexpr (MASKED) {
+            // slot K is the +v direction, slot K + 61 the -v direction
+            constexpr int KB = K + kHalfStencil;
+            constexpr uint32_t BA = 1u << (K % 32), BB = 1u << (KB % 32);
+            exa = exa || (skip[K / 32] & BA) != 0u;
+            exb = exb || (skip[KB / 32] & BB) != 0u;
+            wa = exa ? T(0) : wa;
+            wb = exb ? T(0) : wb;
+            exc[K / 32] |= exa ? BA : 0u;
+            exc[KB / 32] |= exb ? BB : 0u;
         }
         if constexpr (HAS_C) {
             wa = wa * (T(0.5) * (ci + r.ca));
@@ -352,11 +389,38 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
     };
     constexpr int D = sizeof(T) == 4 ? PD_PIPE_DEPTH : 2;
     pipeline<D, FastLoad<T>>(load, comp_pair, std::make_integer_sequence<int, D>{});
-    if constexpr (sizeof(T) == 4) flag = (hi > fmin(thr, T(kSeriesBound))) || (lo < T(-kSeriesBound));
+    if constexpr (MASKED) flag = false;
+    else if constexpr (sizeof(T) == 4) flag = (hi > fmin(thr, T(kSeriesBound))) || (lo < T(-kSeriesBound));
     else flag = hi > thr;
 }
 
-// ---------------------------------------------------------------- history path
+// ---------------------------------------------------------------- exception pass
+// Slot k of the stencil: k < 61 is +kHalf[k], k >= 61 is -kHalf[k - 61].
+// Packed as (x + 3) | (y + 3) << 4 | (z + 3) << 8 | |v|^2 << 12; a block
+// copies the table (and sqrt of the squared lengths) into LDS so that lanes
+// can index it with their own slot.
+constexpr uint32_t pack_slot(int k)
+{
+    const Off o = kHalf.v[k % kHalfStencil];
+    const int sg = k < kHalfStencil ? 1 : -1;
+    return (uint32_t)(sg * o.x + 3) | (uint32_t)(sg * o.y + 3) << 4 | (uint32_t)(sg * o.z + 3) << 8 |
+           (uint32_t)(o.x * o.x + o.y * o.y + o.z * o.z) << 12;
+}
+
+struct SlotPack {
+    uint32_t e[kStencil];
+};
+
+constexpr SlotPack make_slot_pack()
+{
+    SlotPack t{};
+    for (int k = 0; k < kStencil; ++k) t.e[k] = pack_slot(k);
+    return t;
+}
+
+static __constant__ SlotPack c_slot_pack = make_slot_pack();
+
+// the same table unpacked, for loops where every lane takes the same slot
 struct SlotEntry {
     int x, y, z, len2;
 };
@@ -369,9 +433,8 @@ constexpr SlotTable make_slot_table()
 {
     SlotTable t{};
     for (int k = 0; k < kStencil; ++k) {
-        Off o = kHalf.v[k % kHalfStencil];
-        int sg = k < kHalfStencil ? 1 : -1;
-        t.e[k] = SlotEntry{sg * o.x, sg * o.y, sg * o.z, o.x * o.x + o.y * o.y + o.z * o.z};
+        const uint32_t p = pack_slot(k);
+        t.e[k] = SlotEntry{(int)(p & 15u) - 3, (int)((p >> 4) & 15u) - 3, (int)((p >> 8) & 15u) - 3, (int)(p >> 12)};
     }
     return t;
 }
@@ -381,42 +444,67 @@ static __constant__ double c_sqrt_int[10] = {0.0, 1.0, 1.4142135623730951, 1.732
                                              2.23606797749979, 2.449489742783178, 2.6457513110645907,
                                              2.8284271247461903, 3.0};
 
-// Every bond with its damage history: bonds past their limit stretch keep
-// the largest stretch they have seen in hist (never decreasing, so damage
-// never heals); notch-cut bonds and ghost neighbours contribute nothing.
+template <typename T>
+struct SlotLds {
+    uint32_t slot[kStencil];
+    T len[10];
+};
+
+template <typename T>
+__device__ __forceinline__ void fill_slot_lds(SlotLds<T> &t)
+{
+    if (threadIdx.x < kStencil) t.slot[threadIdx.x] = c_slot_pack.e[threadIdx.x];
+    if (threadIdx.x < 10) t.len[threadIdx.x] = (T)c_sqrt_int[threadIdx.x];
+}
+
+// The bonds the masked fast loop left out (todo = its exceptions minus the
+// notch-cut bonds), one at a time in slot order: closed-form stretch,
+// damage history and damage law.  A bond's largest stretch is kept in hist
+// once it passes the bond's limit stretch (never decreasing, so damage never
+// heals), and its bit in dm marks it damaged; a bond whose bit is clear has
+// never passed its limit and has d = 0.  Ghost neighbours contribute nothing.
 template <typename T, bool KAHAN, bool HAS_C, typename Src>
-__device__ __forceinline__ void hist_loop(const StepParams<T> &a, const Src &src, const T *__restrict__ S0,
-                                          const T *__restrict__ Cp, T *__restrict__ Hs, uint32_t lb1,
-                                          int64_t node, const typename Vec4<T>::t &ui, T s0i, T ci, uint4 cm,
-                                          Acc3<T, KAHAN> &acc, bool &dirty)
+__device__ __forceinline__ void exc_loop(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
+                                         const T *__restrict__ S0, const T *__restrict__ Cp, T *__restrict__ Hs,
+                                         uint32_t lb1, int64_t node, const typename Vec4<T>::t &ui, T s0i, T ci,
+                                         const uint32_t (&todo)[4], uint32_t (&dm)[4], Acc3<T, KAHAN> &acc)
 {
     using V4 = typename Vec4<T>::t;
     const uint32_t lbh = (uint32_t)node * (uint32_t)sizeof(T);
-    for (int k = 0; k < kStencil; ++k) {
-        const SlotEntry e = c_slots.e[k];
-        const V4 uj = src.get(e.x, e.y, e.z);
-        const uint32_t bits = k < 32 ? cm.x : k < 64 ? cm.y : k < 96 ? cm.z : cm.w;
-        if (uj.w == T(0) || ((bits >> (k & 31)) & 1u)) continue;
-        const int64_t off = (int64_t)e.x + (int64_t)e.y * a.PX + (int64_t)e.z * a.PXY;
-        T ex, ey, ez, ry;
-        const T num = num_rt<T>(ui, uj, e.x, e.y, e.z, ex, ey, ez);
-        const T s = stretch_from_num(num, T(e.len2), T(c_sqrt_int[e.len2]), ry);
-        const T s0b = T(0.5) * (s0i + ld(S0, off, lb1));
-        T *H = (T *)((char *)(Hs + (int64_t)k * a.M) + lbh);
-        T kap = *H;
-        if (s > kap && s > s0b) {
-            kap = s;
-            *H = s;
+#pragma unroll
+    for (int wd = 0; wd < 4; ++wd) {
+        uint32_t bits = todo[wd];
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1u;
+            const int k = 32 * wd + b;
+            const uint32_t e = tab.slot[k];
+            const int x = (int)(e & 15u) - 3, y = (int)((e >> 4) & 15u) - 3, z = (int)((e >> 8) & 15u) - 3;
+            const int len2 = (int)(e >> 12);
+            const V4 uj = src.get(x, y, z);
+            if (uj.w == T(0)) continue;
+            const int64_t off = (int64_t)x + (int64_t)y * a.PX + (int64_t)z * a.PXY;
+            T ex, ey, ez, ry;
+            const T num = num_rt<T>(ui, uj, x, y, z, ex, ey, ez);
+            const T s = stretch_from_num(num, T(len2), tab.len[len2], ry);
+            const T s0b = T(0.5) * (s0i + ld(S0, off, lb1));
+            const uint32_t bit = 1u << b;
+            T *H = (T *)((char *)(Hs + (int64_t)k * a.M) + lbh);
+            T kap = (dm[wd] & bit) ? *H : T(0);
+            if (s > kap && s > s0b) {
+                kap = s;
+                *H = s;
+                dm[wd] |= bit;
+            }
+            const T cb = HAS_C ? T(0.5) * (ci + ld(Cp, off, lb1)) : T(1);
+            T keep = T(1);
+            if (kap > s0b) {
+                const T sc = s0b + quot(a.gamma_rel, cb * s0b);
+                keep = keep_fraction(a, kap, s0b, sc);
+            }
+            const T w = keep * s * ry * cb;
+            acc.add(w * (T(x) + ex), w * (T(y) + ey), w * (T(z) + ez));
         }
-        const T cb = HAS_C ? T(0.5) * (ci + ld(Cp, off, lb1)) : T(1);
-        T keep = T(1);
-        if (kap > s0b) {
-            dirty = true;
-            const T sc = s0b + quot(a.gamma_rel, cb * s0b);
-            keep = keep_fraction(a, kap, s0b, sc);
-        }
-        const T w = keep * s * ry * cb;
-        acc.add(w * (T(e.x) + ex), w * (T(e.y) + ey), w * (T(e.z) + ez));
     }
 }
 
@@ -468,8 +556,8 @@ __device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int samp
 
 // Forces and Verlet update of one node, given its neighbour source.
 template <typename T, bool KAHAN, bool HAS_C, typename Src>
-__device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src, int sample, int64_t n, int64_t node,
-                                          int64_t p, const typename Vec4<T>::t &ui)
+__device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab, int sample,
+                                          int64_t n, int64_t node, int64_t p, const typename Vec4<T>::t &ui)
 {
     using V4 = typename Vec4<T>::t;
     const T *__restrict__ S0 = a.s0pad + (int64_t)sample * a.P;
@@ -481,18 +569,45 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
 
     Acc3<T, KAHAN> acc;
     acc.zero();
-    bool slow = (ui.w < T(0)) || (inf.cut >= 0);
-    if (!slow) {
-        bool flag = false;
-        fast_loop<T, KAHAN, HAS_C>(a, src, Cp, lb1, ui, ci, a.thr[sm], acc, flag);
-        slow = flag;
+    // A node with a notch-cut bond, or one that has had an exceptional bond
+    // (flag -1, kept from then on), runs the masked fast loop plus the
+    // exception pass; so does every node of its wavefront, which then takes
+    // one pass instead of two.  Other wavefronts run the plain fast loop, and
+    // a node whose plain loop raises the flag is redone in masked form.
+    // FP64 evaluates the closed form on both paths and always takes the
+    // masked one.
+    const bool is_cut = inf.cut >= 0;
+    const bool sticky = ui.w < T(0);
+    bool masked = sizeof(T) == 8 || __any(is_cut || sticky) != 0;
+    if constexpr (sizeof(T) == 4) {
+        if (!masked) {
+            const uint32_t none[4] = {0u, 0u, 0u, 0u};
+            uint32_t unused[4] = {0u, 0u, 0u, 0u};
+            bool flag = false;
+            fast_loop<T, KAHAN, HAS_C, false>(a, src, Cp, lb1, ui, ci, a.thr[sm], acc, flag, none, unused);
+            if (flag) {
+                acc.zero();
+                masked = true;
+            }
+        }
     }
-    bool dirty = false;
-    if (slow) {
-        acc.zero();
-        const uint4 cm = inf.cut >= 0 ? a.cut[inf.cut] : make_uint4(0, 0, 0, 0);
+    bool dirty = sticky;
+    if (masked) {
+        const uint4 cm = is_cut ? a.cut[inf.cut] : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 d0 = sticky ? a.dmask[sm] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t skip[4] = {cm.x | d0.x, cm.y | d0.y, cm.z | d0.z, cm.w | d0.w};
+        uint32_t exc[4] = {0u, 0u, 0u, 0u};
+        T thr = a.thr[sm];
+        if constexpr (sizeof(T) == 4) thr = fmin(thr, T(kSeriesBound3));
+        bool unused = false;
+        fast_loop<T, KAHAN, HAS_C, true>(a, src, Cp, lb1, ui, ci, thr, acc, unused, skip, exc);
+        const uint32_t todo[4] = {exc[0] & ~cm.x, exc[1] & ~cm.y, exc[2] & ~cm.z, exc[3] & ~cm.w};
+        uint32_t dm[4] = {d0.x, d0.y, d0.z, d0.w};
         T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
-        hist_loop<T, KAHAN, HAS_C>(a, src, S0, Cp, Hs, lb1, node, ui, S0[p], ci, cm, acc, dirty);
+        exc_loop<T, KAHAN, HAS_C>(a, src, tab, S0, Cp, Hs, lb1, node, ui, S0[p], ci, todo, dm, acc);
+        if (dm[0] != d0.x || dm[1] != d0.y || dm[2] != d0.z || dm[3] != d0.w)
+            a.dmask[sm] = make_uint4(dm[0], dm[1], dm[2], dm[3]);
+        dirty = dirty || ((exc[0] | exc[1] | exc[2] | exc[3]) != 0u);
     }
     if (a.force_only) {
         double *L = a.L_out + 3 * sm;
@@ -552,6 +667,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams<T> a)
 {
     using V4 = typename Vec4<T>::t;
     __shared__ V4 tile[LDS ? kTileN : 1];
+    __shared__ SlotLds<T> tab;
     const int64_t per_xcd = gridDim.x / kXcds;
     const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
     if (item >= a.n_items) return;
@@ -561,6 +677,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams<T> a)
     if (!a.force_only && t == 0 && n >= 1 && n <= a.n_steps) reduce_previous(a, sample, n);
     if (!a.force_only && n >= a.n_steps) return;   // whole block: finished sample
     const V4 *__restrict__ U = a.u_cur + (int64_t)sample * a.P;
+    fill_slot_lds(tab);
     if constexpr (LDS) {
         const int bx = (int)(t % a.nbx), by = (int)((t / a.nbx) % a.nby), bz = (int)(t / ((int64_t)a.nbx * a.nby));
         // the tile's first padded cell is the brick origin (node + kHalo - kHalo)
@@ -580,8 +697,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams<T> a)
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
         const int c = (tx + kHalo) + kLX * (ty + kHalo) + kLXY * (tz + kHalo);
         const LdsSrc<T> src{tile, c};
-        node_step<T, KAHAN, HAS_C>(a, src, sample, n, node, p, tile[c]);
+        node_step<T, KAHAN, HAS_C>(a, src, tab, sample, n, node, p, tile[c]);
     } else {
+        __syncthreads();
         const int64_t node = t * kBlock + threadIdx.x;
         if (node >= a.M) return;
         const uint32_t nd = (uint32_t)node, nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
@@ -591,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams<T> a)
         const int iy = (int)(r - (uint32_t)iz * ny);
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
         const GlobalSrc<T> src{U, (uint32_t)p * (uint32_t)sizeof(V4), a.PX, a.PXY};
-        node_step<T, KAHAN, HAS_C>(a, src, sample, n, node, p, U[p]);
+        node_step<T, KAHAN, HAS_C>(a, src, tab, sample, n, node, p, U[p]);
     }
 }
 
