@@ -39,7 +39,12 @@ FLOPS_PER_BOND_DIR_F64 = 32          # no compensation
 # used, so 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s.
 PEAK_TFLOPS_F32 = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_TFLOPS_F64 = 78.6
-STEP_KERNEL_F32 = "step_kernel<float, true, false, true>"
+# step-kernel instantiation per launch shape (FP32, compensated, no c field)
+SHAPE_NAMES = ["lds 16x4x4", "lds 8x8x4", "lds 8x4x4", "global 256"]
+SHAPE_KERNELS = ["step_kernel<float, true, false, true, Brick<16, 4, 4>>",
+                 "step_kernel<float, true, false, true, Brick<8, 8, 4>>",
+                 "step_kernel<float, true, false, true, Brick<8, 4, 4>>",
+                 "step_kernel<float, true, false, false, Brick<256, 1, 1>>"]
 
 
 def kernel_source_hash():
@@ -156,6 +161,7 @@ def main():
     s0 = kl.lognormal(xi, W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
     params = B.make_params(lv, precision="f32", accumulate="kahan")
     item = B.BatchItem(mesh, params, S, s0)
+    tune = B.autotune(mesh, params, S)       # the choice run_batch then uses
 
     for _ in range(args.warmup):
         B.run_batch([item])
@@ -202,8 +208,10 @@ def main():
         "time_step_us": avg_launch_s * 1e6,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS_F32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS_F32,
-                     "traffic": traffic, "kernel": STEP_KERNEL_F32,
+                     "traffic": traffic, "kernel": SHAPE_KERNELS[tune["shape"]],
                      "flops_per_launch": flops_per_launch, "avg_launch_us": avg_launch_s * 1e6},
+        "launch_shape": {"chosen": SHAPE_NAMES[tune["shape"]],
+                         "autotune_us_per_step": {n: float(t) for n, t in zip(SHAPE_NAMES, tune["us_per_step"])}},
     }
 
     if not args.no_extras:

@@ -53,6 +53,17 @@ enum { PD_FP32 = 0, PD_FP64 = 1 };
 enum { PD_ACC_KAHAN = 0, PD_ACC_PLAIN = 1 };
 enum { PD_FIELD_S0 = 0, PD_FIELD_C = 1 };
 enum { PD_DTYPE_F32 = 0, PD_DTYPE_F64 = 1 };
+/* Launch shapes of the step kernel: nodes per block as an x-by-y-by-z brick
+ * staged with its halo in LDS, or 256 consecutive nodes read through the
+ * caches.  All shapes give bit-identical results. */
+enum {
+    PD_SHAPE_AUTO = -1,
+    PD_SHAPE_LDS_16x4x4 = 0,
+    PD_SHAPE_LDS_8x8x4 = 1,
+    PD_SHAPE_LDS_8x4x4 = 2,
+    PD_SHAPE_GLOBAL_256 = 3,
+    PD_N_SHAPES = 4
+};
 
 typedef struct pd_mesh_s *pd_mesh;
 typedef struct pd_run_s *pd_run_h;
@@ -187,6 +198,27 @@ typedef struct {
 } pd_batch_item;
 
 PD_API int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream);
+
+/* Launch-shape autotuner (no paper counterpart: it only changes how the
+ * work of one time step is mapped onto the GPU).  Measures every shape that
+ * the configuration (mesh dims, n_samples, p->precision, p->accumulate,
+ * micromodulus field set or not) can use over a few time steps of a
+ * throw-away solve with homogeneous fields, caches the fastest for the rest
+ * of the process, and returns it in *shape_out; us_per_step_out (nullable,
+ * host FP64 [PD_N_SHAPES]) receives each shape's time per step (-1 for shapes
+ * the configuration cannot use).  FP64 has one shape (PD_SHAPE_GLOBAL_256).
+ * pd_run and pd_run_batch tune a configuration the same way the first time
+ * they meet it, unless the mesh has a pinned shape.  Synchronous on
+ * stream; allocates a solve's buffers for the duration of the call. */
+PD_API int pd_autotune(pd_mesh m, const pd_params *p, int64_t n_samples, void *stream, int32_t *shape_out,
+                       double *us_per_step_out);
+
+/* Pins the launch shape of every later run on this mesh (PD_SHAPE_AUTO
+ * restores tuning).  Shapes a configuration cannot use fall back to one it
+ * can (FP64: PD_SHAPE_GLOBAL_256; PD_ACC_PLAIN or a micromodulus field: the
+ * 16x4x4 brick or the global shape).  Fails with PD_EINVAL for an unknown
+ * shape. */
+PD_API int pd_set_launch_shape(pd_mesh m, int32_t shape);
 
 /* Gradient of the peak reaction Q = R^{n*} with respect to the per-node
  * limit-stretch field s0 and micromodulus field c, by a hand-written

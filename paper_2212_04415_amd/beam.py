@@ -52,6 +52,11 @@ class Mesh:
         n = v.size // self.n_nodes
         pd.pd_set_material_field(self.h, field, n, v.ctypes.data, 0, pd.PD_DTYPE_F64, None)
 
+    def set_launch_shape(self, shape: int):
+        """Pin the step kernel's launch shape (pd.PD_SHAPE_*), or
+        pd.PD_SHAPE_AUTO to let the autotuner choose."""
+        pd.pd_set_launch_shape(self.h, shape)
+
     def close(self):
         if self.h:
             pd.pd_free_mesh(self.h)
@@ -192,6 +197,15 @@ def level_stats(q_fine, q_coarse=None, stream=None):
     pd.pd_level_stats(q_fine.data_ptr(), q_coarse.data_ptr() if q_coarse is not None else None,
                       q_fine.numel(), sums.data_ptr(), _stream_ptr(stream))
     return sums
+
+
+def autotune(mesh: Mesh, params, n_samples: int, stream=None):
+    """pd_autotune: the fastest launch shape of this configuration and the
+    time per step of every shape (-1 where the configuration cannot use it)."""
+    shape = C.c_int32()
+    us = np.zeros(pd.PD_N_SHAPES)
+    pd.pd_autotune(mesh.h, C.byref(params), n_samples, _stream_ptr(stream), C.byref(shape), us.ctypes.data)
+    return dict(shape=shape.value, us_per_step=us)
 
 
 def qoi_grad(mesh: Mesh, params, s0=None, c=None, stream=None):

@@ -1,0 +1,12 @@
+// Step-kernel instantiations: launch_f32_kahan.
+#define PD_STEP_LAUNCH_IMPL
+#include "step_launch.h"
+
+namespace pdmi {
+
+void launch_f32_kahan(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a)
+{
+    launch_shape<float, true, false>(shape, grid, st, a);
+}
+
+}  // namespace pdmi

@@ -111,6 +111,8 @@ struct pd_mesh_s {
     double *d_c = nullptr;
     int64_t c_samples = 0;
 
+    int shape_override = -1;   // pinned launch shape (PD_SHAPE_*), -1 = tuned
+
     int64_t padded(int i, int j, int k) const
     {
         return (int64_t)(i + pdmi::kHalo) + (int64_t)PX * ((j + pdmi::kHalo) + (int64_t)PY * (k + pdmi::kHalo));

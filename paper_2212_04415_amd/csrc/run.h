@@ -8,6 +8,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -164,6 +167,20 @@ static int alloc_run(const pd_mesh_s *m, int S, bool f64, bool kahan, bool has_c
     return PD_OK;
 }
 
+// Launch shapes of the step kernel (brick of nodes per block, LDS tile or
+// not).  Every shape computes bit-identical results; the autotuner picks the
+// fastest per configuration.  FP64 always uses the global shape.
+struct LaunchShape {
+    int bx, by, bz, threads;
+    bool lds;
+};
+constexpr LaunchShape kShapes[PD_N_SHAPES] = {
+    {16, 4, 4, 256, true},   // PD_SHAPE_LDS_16x4x4
+    {8, 8, 4, 256, true},    // PD_SHAPE_LDS_8x8x4
+    {8, 4, 4, 128, true},    // PD_SHAPE_LDS_8x4x4
+    {256, 1, 1, 256, false}, // PD_SHAPE_GLOBAL_256
+};
+
 // Common state of one (mesh, params, samples) solve.
 struct Solve {
     const pd_mesh_s *m;
@@ -171,15 +188,18 @@ struct Solve {
     Material mat;
     RunBuffers b;
     int64_t n_steps;
+    int shape = PD_SHAPE_LDS_16x4x4;
 };
 
-// FP32 steps read neighbours from an LDS brick; FP64 (a single-sample,
-// latency-bound solve) reads them through the caches.
-#ifndef PD_FP32_LDS
-#define PD_FP32_LDS 1
-#endif
-template <typename T>
-constexpr bool use_lds() { return sizeof(T) == 4 && PD_FP32_LDS; }
+// The shape a solve can actually launch with: FP64 has the global shape
+// only; uncompensated accumulation (an ablation) and micromodulus fields
+// have the default brick and the global shape.
+static int effective_shape(bool f64, bool kahan, bool has_c, int shape)
+{
+    if (f64) return PD_SHAPE_GLOBAL_256;
+    if ((!kahan || has_c) && shape != PD_SHAPE_GLOBAL_256) return PD_SHAPE_LDS_16x4x4;
+    return shape;
+}
 
 template <typename T>
 static StepParams<T> make_step_params(const Solve &s, int k_local)
@@ -214,10 +234,11 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     a.P = m->P;
     a.M = m->M;
     a.PXY = (int64_t)m->PX * m->PY;
-    a.nbx = (m->nx + kBX - 1) / kBX;
-    a.nby = (m->ny + kBY - 1) / kBY;
-    const int64_t nbz = (m->nz + kBZ - 1) / kBZ;
-    a.tiles = use_lds<T>() ? (int64_t)a.nbx * a.nby * nbz : (m->M + kBlock - 1) / kBlock;
+    const LaunchShape &sh = kShapes[effective_shape(b.f64, b.kahan, b.has_c, s.shape)];
+    a.nbx = (m->nx + sh.bx - 1) / sh.bx;
+    a.nby = (m->ny + sh.by - 1) / sh.by;
+    const int64_t nbz = (m->nz + sh.bz - 1) / sh.bz;
+    a.tiles = sh.lds ? (int64_t)a.nbx * a.nby * nbz : (m->M + sh.threads - 1) / sh.threads;
     a.n_items = a.tiles * b.S;
     a.nz = m->nz;
     a.PY = m->PY;
@@ -249,28 +270,16 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     return a;
 }
 
+// One step launch of a solve (defined with the kernel instantiations in
+// solver.hip).  L_out != null: force-only evaluation into L_out.
+void launch_step_f32(const Solve &s, int k_local, hipStream_t st, double *L_out);
+void launch_step_f64(const Solve &s, int k_local, hipStream_t st, double *L_out);
+
 template <typename T>
-static void launch_step(const Solve &s, int k_local, hipStream_t st, double *L_out = nullptr)
+static inline void launch_step(const Solve &s, int k_local, hipStream_t st, double *L_out = nullptr)
 {
-    StepParams<T> a = make_step_params<T>(s, k_local);
-    if (L_out) {
-        a.L_out = L_out;
-        a.force_only = 1;
-    }
-    const int64_t items = a.n_items;
-    dim3 grid((unsigned)((items + kXcds - 1) / kXcds * kXcds));
-    if constexpr (std::is_same<T, float>::value) {
-        if (s.b.kahan) {
-            if (s.b.has_c) step_kernel<float, true, true, use_lds<T>()><<<grid, kBlock, 0, st>>>(a);
-            else step_kernel<float, true, false, use_lds<T>()><<<grid, kBlock, 0, st>>>(a);
-        } else {
-            if (s.b.has_c) step_kernel<float, false, true, use_lds<T>()><<<grid, kBlock, 0, st>>>(a);
-            else step_kernel<float, false, false, use_lds<T>()><<<grid, kBlock, 0, st>>>(a);
-        }
-    } else {
-        if (s.b.has_c) step_kernel<double, false, true, false><<<grid, kBlock, 0, st>>>(a);
-        else step_kernel<double, false, false, false><<<grid, kBlock, 0, st>>>(a);
-    }
+    if constexpr (sizeof(T) == 4) launch_step_f32(s, k_local, st, L_out);
+    else launch_step_f64(s, k_local, st, L_out);
 }
 
 static void launch_advance(const Solve &s, int64_t by, hipStream_t st)
@@ -395,6 +404,116 @@ static int enqueue_steps(const Solve &s, hipStream_t st, std::vector<hipGraphExe
     for (int64_t k = full * kChunk; k <= N; ++k) launch_step<T>(s, (int)(k - full * kChunk), st);
     PD_HIP(hipGetLastError());
     return PD_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Launch-shape choice per (grid dims, samples, precision, accumulation,
+// micromodulus field), measured once per process and cached.
+using TuneKey = std::tuple<int, int, int, int64_t, bool, bool, bool>;
+
+struct TuneCache {
+    std::mutex mu;
+    std::map<TuneKey, int> best;
+};
+
+static TuneCache &tune_cache()
+{
+    static TuneCache c;
+    return c;
+}
+
+static TuneKey tune_key(const Solve &s)
+{
+    return TuneKey{s.m->nx, s.m->ny, s.m->nz, (int64_t)s.b.S, s.b.f64, s.b.kahan, s.b.has_c};
+}
+
+// Times `reps` steps of every shape on the solve's buffers (after two
+// warm-up steps each) and returns the fastest.  The solve's state advances:
+// the caller re-initialises it afterwards.  Synchronises the stream.
+template <typename T>
+static int autotune_shapes(const Solve &s, hipStream_t st, int reps, int *best_out, double *us_out)
+{
+    Solve t = s;                  // same buffers; no history, no step limit
+    t.n_steps = (int64_t)1 << 40;
+    t.b.hist_R = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PD_HIP(hipEventCreate(&e0));
+    PD_HIP(hipEventCreate(&e1));
+    int best = -1;
+    float best_ms = 0.f;
+    int k = 0;
+    int rc = PD_OK;
+    for (int sh = 0; sh < PD_N_SHAPES && rc == PD_OK; ++sh) {
+        if (us_out) us_out[sh] = -1.0;
+        if (effective_shape(t.b.f64, t.b.kahan, t.b.has_c, sh) != sh) continue;
+        t.shape = sh;
+        for (int w = 0; w < 2; ++w) launch_step<T>(t, k++, st);
+        hipError_t e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) launch_step<T>(t, k++, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune");
+            break;
+        }
+        if (us_out) us_out[sh] = 1000.0 * ms / reps;
+        if (best < 0 || ms < best_ms) {
+            best = sh;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == PD_OK && best_out) *best_out = best;
+    return rc;
+}
+
+// The launch shape of a solve without measuring: the pinned one, else the
+// cached choice, else the default brick.
+static int known_shape(const Solve &s)
+{
+    if (s.m->shape_override >= 0) return effective_shape(s.b.f64, s.b.kahan, s.b.has_c, s.m->shape_override);
+    if (s.b.f64) return PD_SHAPE_GLOBAL_256;
+    std::lock_guard<std::mutex> g(tune_cache().mu);
+    auto it = tune_cache().best.find(tune_key(s));
+    return it != tune_cache().best.end() ? it->second : PD_SHAPE_LDS_16x4x4;
+}
+
+// Picks the launch shape of a set-up solve: the mesh's pinned shape, else the
+// cached choice, else a fresh measurement (after which the solve is set up
+// again from scratch, so the measurement leaves no trace in the results).
+template <typename T, typename In>
+static int choose_shape(Solve &s, const In *s0, int64_t s0_stride, const In *c, int64_t c_stride, hipStream_t st)
+{
+    if (s.b.f64) {
+        s.shape = PD_SHAPE_GLOBAL_256;
+        return PD_OK;
+    }
+    if (s.m->shape_override >= 0) {
+        s.shape = effective_shape(s.b.f64, s.b.kahan, s.b.has_c, s.m->shape_override);
+        return PD_OK;
+    }
+    const TuneKey key = tune_key(s);
+    {
+        std::lock_guard<std::mutex> g(tune_cache().mu);
+        auto it = tune_cache().best.find(key);
+        if (it != tune_cache().best.end()) {
+            s.shape = it->second;
+            return PD_OK;
+        }
+    }
+    int best = PD_SHAPE_LDS_16x4x4;
+    int rc = autotune_shapes<T>(s, st, 8, &best, nullptr);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> g(tune_cache().mu);
+        tune_cache().best[key] = best;
+    }
+    s.shape = best;
+    return setup_solve<T, In>(s, s0, s0_stride, c, c_stride, st);
 }
 
 }  // namespace pdmi

@@ -12,10 +12,45 @@
 
 #include "pd_internal.h"
 #include "run.h"
+#include "step_launch.h"
 
 namespace pdmi {
 
 const char *last_error();
+
+template <typename T>
+static void launch_step_impl(const Solve &s, int k_local, hipStream_t st, double *L_out)
+{
+    StepParams<T> a = make_step_params<T>(s, k_local);
+    if (L_out) {
+        a.L_out = L_out;
+        a.force_only = 1;
+    }
+    dim3 grid((unsigned)((a.n_items + kXcds - 1) / kXcds * kXcds));
+    const int shape = effective_shape(s.b.f64, s.b.kahan, s.b.has_c, s.shape);
+    if constexpr (sizeof(T) == 4) {
+        if (s.b.kahan) {
+            if (s.b.has_c) launch_f32_kahan_c(shape, grid, st, a);
+            else launch_f32_kahan(shape, grid, st, a);
+        } else {
+            if (s.b.has_c) launch_f32_plain_c(shape, grid, st, a);
+            else launch_f32_plain(shape, grid, st, a);
+        }
+    } else {
+        if (s.b.has_c) launch_f64_c(shape, grid, st, a);
+        else launch_f64(shape, grid, st, a);
+    }
+}
+
+void launch_step_f32(const Solve &s, int k_local, hipStream_t st, double *L_out)
+{
+    launch_step_impl<float>(s, k_local, st, L_out);
+}
+
+void launch_step_f64(const Solve &s, int k_local, hipStream_t st, double *L_out)
+{
+    launch_step_impl<double>(s, k_local, st, L_out);
+}
 
 }  // namespace pdmi
 
@@ -159,6 +194,7 @@ int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double
         if (f64) rc = setup_solve<double>(s, m->d_s0, m->M, m->d_c, m->M, st);
         else rc = setup_solve<float>(s, m->d_s0, m->M, m->d_c, m->M, st);
         if (rc) break;
+        s.shape = known_shape(s);
         // displacements into the padded grid (units of dx), flag 1
         host.assign(ts * 4 * m->P * n_samples, 0);
         for (int64_t smp = 0; smp < n_samples; ++smp)
@@ -214,6 +250,8 @@ int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out)
                    r->s.b, true);
     if (!rc) rc = f64 ? setup_solve<double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream)
                       : setup_solve<float>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream);
+    if (!rc) rc = f64 ? choose_shape<double, double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream)
+                      : choose_shape<float, double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream);
     if (!rc) rc = f64 ? enqueue_steps<double>(r->s, r->stream, r->graphs) : enqueue_steps<float>(r->s, r->stream, r->graphs);
     if (rc) {
         (void)hipStreamSynchronize(r->stream);
@@ -288,6 +326,45 @@ int pd_free_run(pd_run_h r)
     return PD_OK;
 }
 
+int pd_set_launch_shape(pd_mesh m, int32_t shape)
+{
+    if (!m) return fail(PD_EINVAL, "null mesh");
+    if (shape < PD_SHAPE_AUTO || shape >= PD_N_SHAPES) return fail(PD_EINVAL, "unknown launch shape %d", shape);
+    m->shape_override = shape;
+    return PD_OK;
+}
+
+int pd_autotune(pd_mesh m, const pd_params *p, int64_t n_samples, void *stream, int32_t *shape_out,
+                double *us_per_step_out)
+{
+    if (!m || !p) return fail(PD_EINVAL, "null argument");
+    if (n_samples < 1 || n_samples > 65535) return fail(PD_EINVAL, "n_samples out of range");
+    int rc = ensure_device(m);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Solve s{};
+    s.m = m;
+    s.p = *p;
+    s.n_steps = p->n_steps;
+    if ((rc = check_params(m, p, &s.mat))) return rc;
+    const bool f64 = p->precision == PD_FP64;
+    rc = alloc_run(m, (int)n_samples, f64, p->accumulate == PD_ACC_KAHAN, false, false, 0, s.b, true);
+    int best = PD_SHAPE_GLOBAL_256;
+    if (!rc) rc = f64 ? setup_solve<double>(s, (const double *)nullptr, 0, (const double *)nullptr, 0, st)
+                      : setup_solve<float>(s, (const double *)nullptr, 0, (const double *)nullptr, 0, st);
+    if (!rc) rc = f64 ? autotune_shapes<double>(s, st, 8, &best, us_per_step_out)
+                      : autotune_shapes<float>(s, st, 8, &best, us_per_step_out);
+    (void)hipStreamSynchronize(st);
+    s.b.release();
+    if (rc) return rc;
+    if (!f64) {
+        std::lock_guard<std::mutex> g(tune_cache().mu);
+        tune_cache().best[tune_key(s)] = best;
+    }
+    if (shape_out) *shape_out = best;
+    return PD_OK;
+}
+
 static int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
 
 int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
@@ -341,12 +418,15 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         if (!rc && !s.b.status) rc = s.b.alloc((void **)&s.b.status, 4 * it.n_samples);
         if (rc) break;
         int64_t M = it.mesh->M;
-        if (it.field_dtype == PD_DTYPE_F64)
-            rc = f64 ? setup_solve<double, double>(s, (const double *)it.s0, M, (const double *)it.c, M, st)
-                     : setup_solve<float, double>(s, (const double *)it.s0, M, (const double *)it.c, M, st);
-        else
-            rc = f64 ? setup_solve<double, float>(s, (const float *)it.s0, M, (const float *)it.c, M, st)
-                     : setup_solve<float, float>(s, (const float *)it.s0, M, (const float *)it.c, M, st);
+        if (it.field_dtype == PD_DTYPE_F64) {
+            const double *s0 = (const double *)it.s0, *c = (const double *)it.c;
+            rc = f64 ? setup_solve<double, double>(s, s0, M, c, M, st) : setup_solve<float, double>(s, s0, M, c, M, st);
+            if (!rc) rc = f64 ? choose_shape<double, double>(s, s0, M, c, M, st) : choose_shape<float, double>(s, s0, M, c, M, st);
+        } else {
+            const float *s0 = (const float *)it.s0, *c = (const float *)it.c;
+            rc = f64 ? setup_solve<double, float>(s, s0, M, c, M, st) : setup_solve<float, float>(s, s0, M, c, M, st);
+            if (!rc) rc = f64 ? choose_shape<double, float>(s, s0, M, c, M, st) : choose_shape<float, float>(s, s0, M, c, M, st);
+        }
     }
     hipGraphExec_t exec = nullptr;
     if (!rc && ticks > 0) {

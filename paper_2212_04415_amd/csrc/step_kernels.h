@@ -30,24 +30,26 @@
 
 #include "pd_internal.h"
 
-#ifndef PD_BLOCK
-#define PD_BLOCK 256
-#endif
 #ifndef PD_PIPE_DEPTH
 #define PD_PIPE_DEPTH 4
 #endif
 
 namespace pdmi {
 
-constexpr int kBlock = PD_BLOCK;
 constexpr int kXcds = 8;
 
-// brick of nodes per block on the LDS path, and its tile with the halo
-constexpr int kBX = 16, kBY = 4, kBZ = 4;
-static_assert(kBX * kBY * kBZ == kBlock, "brick must match the block");
-constexpr int kLX = kBX + 2 * kHalo, kLY = kBY + 2 * kHalo, kLZ = kBZ + 2 * kHalo;
-constexpr int kLXY = kLX * kLY;
-constexpr int kTileN = kLX * kLY * kLZ;
+// Brick of nodes owned by one block (one thread per node, x fastest) and, on
+// the LDS path, its tile with the kHalo-wide halo.  The global path uses the
+// thread count only (a tile is N consecutive nodes).
+template <int BX_, int BY_, int BZ_>
+struct Brick {
+    static constexpr int BX = BX_, BY = BY_, BZ = BZ_;
+    static constexpr int N = BX * BY * BZ;
+    static constexpr int LX = BX + 2 * kHalo, LY = BY + 2 * kHalo, LZ = BZ + 2 * kHalo;
+    static constexpr int LXY = LX * LY;
+    static constexpr int TILE = LX * LY * LZ;
+    static_assert(N % 64 == 0, "a brick is whole wavefronts");
+};
 
 // sqrt(n) for the squared lengths that occur in the stencil
 constexpr double kSqrtInt[10] = {0.0, 1.0, 1.4142135623730951, 1.7320508075688772, 2.0,
@@ -227,16 +229,16 @@ struct GlobalSrc {
 };
 
 // ... from the block's LDS tile (brick plus halo)
-template <typename T>
+template <typename T, typename BR>
 struct LdsSrc {
     using V4 = typename Vec4<T>::t;
     const V4 *tile;
     int c;
     template <int X, int Y, int Z> __device__ __forceinline__ V4 get() const
     {
-        return tile[c + X + kLX * Y + kLXY * Z];
+        return tile[c + X + BR::LX * Y + BR::LXY * Z];
     }
-    __device__ __forceinline__ V4 get(int x, int y, int z) const { return tile[c + x + kLX * y + kLXY * z]; }
+    __device__ __forceinline__ V4 get(int x, int y, int z) const { return tile[c + x + BR::LX * y + BR::LXY * z]; }
 };
 
 // ---------------------------------------------------------------- pipelining
@@ -274,25 +276,27 @@ template <typename T> struct FastLoad {
 //
 // Plain form (MASKED = false): all bonds of the node are known to be below
 // their limit stretch (d = 0); flag is raised when a bond may have reached the
-// node's lower bound of limit stretches (or is compressed beyond 2^-13), and
-// the node is then redone in masked form.
+// node's lower bound of limit stretches (or leaves the series range), and the
+// node is then redone in masked form.
 //
 // Masked form: bonds listed in `skip` (notch-cut or damaged) and bonds that
 // reach the threshold or leave the series range contribute nothing here and
 // are returned in `exc` (a superset of `skip`) for the exception pass.
+//
+// The two forms evaluate an in-range bond identically and flag exactly the
+// bonds the other would except, so a node's result does not depend on which
+// form its wavefront takes (nor, therefore, on the brick shape of the launch).
 //
 // In FP32 the stretch and the force weight w = s / |v + e| of an undamaged
 // bond are evaluated without square root or division: with x = num / (2|v|^2),
 // |v + e| = |v| sqrt(1 + 2x), so
 //   s = sqrt(1 + 2x) - 1 <= x,
 //   w = (1 - (1 + 2x)^(-1/2)) / |v| = (x / |v|)(1 - 3/2 x + 5/2 x^2 - 35/8 x^3 ...).
-// The plain form keeps two terms for |x| < 2^-13 (larger tensions are flagged
-// through s <= x, larger compressions explicitly): relative error below
-// 5/2 * 2^-26 = 3.7e-8, under FP32 rounding (2^-24 = 6e-8).  The masked form
-// keeps three terms for |x| < 2^-10: error below 35/8 * 2^-30 = 4.1e-9.  FP64
-// and the exception pass use the closed form.
-constexpr double kSeriesBound = 1.0 / 8192;
-constexpr double kSeriesBound3 = 1.0 / 1024;
+// Three terms are kept for |x| < 2^-10 (larger tensions are caught through
+// s <= x by the threshold, which is clamped to 2^-10, larger compressions
+// explicitly): relative error below 35/8 * 2^-30 = 4.1e-9, under FP32
+// rounding (2^-24 = 6e-8).  FP64 and the exception pass use the closed form.
+constexpr double kSeriesBound = 1.0 / 1024;
 
 template <typename T, bool KAHAN, bool HAS_C, bool MASKED, typename Src>
 __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src, const T *__restrict__ Cp,
@@ -329,17 +333,15 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
             const T xwa = xa * fabs(r.a.w), xwb = xb * fabs(r.b.w);
             constexpr T IV = T(1.0 / kSqrtInt[V2]);
             constexpr T IV15 = T(-1.5 / kSqrtInt[V2]);
+            constexpr T IV25 = T(2.5 / kSqrtInt[V2]);
+            wa = xwa * fma_(xa, fma_(xa, IV25, IV15), IV);
+            wb = xwb * fma_(xb, fma_(xb, IV25, IV15), IV);
             if constexpr (MASKED) {
-                constexpr T IV25 = T(2.5 / kSqrtInt[V2]);
-                exa = (xwa > thr) || (xwa < T(-kSeriesBound3));
-                exb = (xwb > thr) || (xwb < T(-kSeriesBound3));
-                wa = xwa * fma_(xa, fma_(xa, IV25, IV15), IV);
-                wb = xwb * fma_(xb, fma_(xb, IV25, IV15), IV);
+                exa = (xwa > thr) || (xwa < T(-kSeriesBound));
+                exb = (xwb > thr) || (xwb < T(-kSeriesBound));
             } else {
                 hi = fmax(hi, fmax(xwa, xwb));
                 lo = fmin(lo, fmin(xwa, xwb));
-                wa = xwa * fma_(xa, IV15, IV);
-                wb = xwb * fma_(xb, IV15, IV);
             }
         } else {
             T rya, ryb;
@@ -390,7 +392,7 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
     constexpr int D = sizeof(T) == 4 ? PD_PIPE_DEPTH : 2;
     pipeline<D, FastLoad<T>>(load, comp_pair, std::make_integer_sequence<int, D>{});
     if constexpr (MASKED) flag = false;
-    else if constexpr (sizeof(T) == 4) flag = (hi > fmin(thr, T(kSeriesBound))) || (lo < T(-kSeriesBound));
+    else if constexpr (sizeof(T) == 4) flag = (hi > thr) || (lo < T(-kSeriesBound));
     else flag = hi > thr;
 }
 
@@ -527,19 +529,21 @@ __device__ __forceinline__ void kick_drift(const StepParams<T> &a, T G, T &vh, T
 // each sample: the support-node forces of a step are written to one half of
 // a double buffer and summed in FP64 by the next launch, so the kernel
 // boundary orders the writes before the reads (no device-wide fences).  The
-// sum runs in a fixed order (a strided pass per thread, then a fixed tree),
-// so R does not depend on scheduling.
-template <typename T>
+// sum runs in a fixed order (a strided pass over 64 lanes, then a fixed
+// tree), so R depends neither on scheduling nor on the block size.
+template <typename T, int NT>
 __device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int sample, int64_t n)
 {
-    __shared__ double part[kBlock];
+    __shared__ double part[64];
     const int64_t prev = n - 1;
-    double sum = 0.0;
     const double *rf = a.rf + ((int64_t)(prev & 1) * a.rf_stride) + (int64_t)sample * a.nsup;
-    for (int i = threadIdx.x; i < a.nsup; i += kBlock) sum += rf[i];
-    part[threadIdx.x] = sum;
+    if (threadIdx.x < 64) {
+        double sum = 0.0;
+        for (int i = threadIdx.x; i < a.nsup; i += 64) sum += rf[i];
+        part[threadIdx.x] = sum;
+    }
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (int w = 32; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
@@ -578,13 +582,15 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
     // masked one.
     const bool is_cut = inf.cut >= 0;
     const bool sticky = ui.w < T(0);
+    T thr = a.thr[sm];
+    if constexpr (sizeof(T) == 4) thr = fmin(thr, T(kSeriesBound));
     bool masked = sizeof(T) == 8 || __any(is_cut || sticky) != 0;
     if constexpr (sizeof(T) == 4) {
         if (!masked) {
             const uint32_t none[4] = {0u, 0u, 0u, 0u};
             uint32_t unused[4] = {0u, 0u, 0u, 0u};
             bool flag = false;
-            fast_loop<T, KAHAN, HAS_C, false>(a, src, Cp, lb1, ui, ci, a.thr[sm], acc, flag, none, unused);
+            fast_loop<T, KAHAN, HAS_C, false>(a, src, Cp, lb1, ui, ci, thr, acc, flag, none, unused);
             if (flag) {
                 acc.zero();
                 masked = true;
@@ -597,8 +603,6 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         const uint4 d0 = sticky ? a.dmask[sm] : make_uint4(0u, 0u, 0u, 0u);
         const uint32_t skip[4] = {cm.x | d0.x, cm.y | d0.y, cm.z | d0.z, cm.w | d0.w};
         uint32_t exc[4] = {0u, 0u, 0u, 0u};
-        T thr = a.thr[sm];
-        if constexpr (sizeof(T) == 4) thr = fmin(thr, T(kSeriesBound3));
         bool unused = false;
         fast_loop<T, KAHAN, HAS_C, true>(a, src, Cp, lb1, ui, ci, thr, acc, unused, skip, exc);
         const uint32_t todo[4] = {exc[0] & ~cm.x, exc[1] & ~cm.y, exc[2] & ~cm.z, exc[3] & ~cm.w};
@@ -653,20 +657,20 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
 }
 
 // One time step for every (sample, tile) work item.
-//   LDS = false: a tile is kBlock consecutive nodes; neighbours come from the
+//   LDS = false: a tile is BR::N consecutive nodes; neighbours come from the
 //                padded grid through the caches.
-//   LDS = true : a tile is a kBX x kBY x kBZ brick; the block first copies the
-//                brick and its kHalo-wide halo into LDS, then reads every
+//   LDS = true : a tile is a BR::BX x BY x BZ brick; the block first copies
+//                the brick and its kHalo-wide halo into LDS, then reads every
 //                neighbour from there.
 // Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8); each
 // XCD is given a contiguous range of work items so the halo a tile shares with
 // its neighbours stays in that XCD's L2.  The grid is padded to a multiple of
 // 8 and surplus blocks exit.
-template <typename T, bool KAHAN, bool HAS_C, bool LDS>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepParams<T> a)
+template <typename T, bool KAHAN, bool HAS_C, bool LDS, typename BR>
+__global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
 {
     using V4 = typename Vec4<T>::t;
-    __shared__ V4 tile[LDS ? kTileN : 1];
+    __shared__ V4 tile[LDS ? BR::TILE : 1];
     __shared__ SlotLds<T> tab;
     const int64_t per_xcd = gridDim.x / kXcds;
     const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
@@ -674,33 +678,33 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams<T> a)
     const int sample = (int)(item / a.tiles);
     const int64_t t = item % a.tiles;
     const int64_t n = a.step_base[sample] + a.k_local;
-    if (!a.force_only && t == 0 && n >= 1 && n <= a.n_steps) reduce_previous(a, sample, n);
+    if (!a.force_only && t == 0 && n >= 1 && n <= a.n_steps) reduce_previous<T, BR::N>(a, sample, n);
     if (!a.force_only && n >= a.n_steps) return;   // whole block: finished sample
     const V4 *__restrict__ U = a.u_cur + (int64_t)sample * a.P;
     fill_slot_lds(tab);
     if constexpr (LDS) {
         const int bx = (int)(t % a.nbx), by = (int)((t / a.nbx) % a.nby), bz = (int)(t / ((int64_t)a.nbx * a.nby));
         // the tile's first padded cell is the brick origin (node + kHalo - kHalo)
-        const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
-        for (int q = threadIdx.x; q < kTileN; q += kBlock) {
-            const int lx = q % kLX, ly = (q / kLX) % kLY, lz = q / kLXY;
+        const int x0 = bx * BR::BX, y0 = by * BR::BY, z0 = bz * BR::BZ;
+        for (int q = threadIdx.x; q < BR::TILE; q += BR::N) {
+            const int lx = q % BR::LX, ly = (q / BR::LX) % BR::LY, lz = q / BR::LXY;
             const int px = x0 + lx, py = y0 + ly, pz = z0 + lz;
             V4 v{};
             if (px < a.PX && py < a.PY && pz < a.PZ) v = U[px + (int64_t)py * a.PX + (int64_t)pz * a.PXY];
             tile[q] = v;
         }
         __syncthreads();
-        const int tx = threadIdx.x % kBX, ty = (threadIdx.x / kBX) % kBY, tz = threadIdx.x / (kBX * kBY);
+        const int tx = threadIdx.x % BR::BX, ty = (threadIdx.x / BR::BX) % BR::BY, tz = threadIdx.x / (BR::BX * BR::BY);
         const int ix = x0 + tx, iy = y0 + ty, iz = z0 + tz;
         if (ix >= a.nx || iy >= a.ny || iz >= a.nz) return;
         const int64_t node = ix + (int64_t)a.nx * (iy + (int64_t)a.ny * iz);
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
-        const int c = (tx + kHalo) + kLX * (ty + kHalo) + kLXY * (tz + kHalo);
-        const LdsSrc<T> src{tile, c};
+        const int c = (tx + kHalo) + BR::LX * (ty + kHalo) + BR::LXY * (tz + kHalo);
+        const LdsSrc<T, BR> src{tile, c};
         node_step<T, KAHAN, HAS_C>(a, src, tab, sample, n, node, p, tile[c]);
     } else {
         __syncthreads();
-        const int64_t node = t * kBlock + threadIdx.x;
+        const int64_t node = t * BR::N + threadIdx.x;
         if (node >= a.M) return;
         const uint32_t nd = (uint32_t)node, nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
         const uint32_t r = nd / nx;

@@ -1,0 +1,42 @@
+// Launches of the step kernel for each launch shape.  The kernel
+// instantiations are spread over several translation units (one per
+// precision / accumulation / micromodulus combination) so they compile in
+// parallel; each defines one of the functions declared at the end.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pd_internal.h"
+#include "step_kernels.h"
+
+namespace pdmi {
+
+#ifdef PD_STEP_LAUNCH_IMPL
+template <typename T, bool KAHAN, bool HAS_C>
+static void launch_shape(int shape, dim3 grid, hipStream_t st, const StepParams<T> &a)
+{
+    if constexpr (sizeof(T) == 4 && KAHAN && !HAS_C) {
+        switch (shape) {
+        case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4>><<<grid, 256, 0, st>>>(a); return;
+        case PD_SHAPE_LDS_8x8x4: step_kernel<T, KAHAN, HAS_C, true, Brick<8, 8, 4>><<<grid, 256, 0, st>>>(a); return;
+        case PD_SHAPE_LDS_8x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<8, 4, 4>><<<grid, 128, 0, st>>>(a); return;
+        default: break;
+        }
+    } else if constexpr (sizeof(T) == 4) {
+        if (shape == PD_SHAPE_LDS_16x4x4) {
+            step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4>><<<grid, 256, 0, st>>>(a);
+            return;
+        }
+    }
+    step_kernel<T, KAHAN, HAS_C, false, Brick<256, 1, 1>><<<grid, 256, 0, st>>>(a);
+}
+#endif
+
+void launch_f32_kahan(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f32_kahan_c(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f32_plain(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f32_plain_c(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f64(int shape, dim3 grid, hipStream_t st, const StepParams<double> &a);
+void launch_f64_c(int shape, dim3 grid, hipStream_t st, const StepParams<double> &a);
+
+}  // namespace pdmi

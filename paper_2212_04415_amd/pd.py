@@ -17,6 +17,8 @@ PD_FP32, PD_FP64 = 0, 1
 PD_ACC_KAHAN, PD_ACC_PLAIN = 0, 1
 PD_FIELD_S0, PD_FIELD_C = 0, 1
 PD_DTYPE_F32, PD_DTYPE_F64 = 0, 1
+PD_SHAPE_AUTO, PD_SHAPE_LDS_16x4x4, PD_SHAPE_LDS_8x8x4, PD_SHAPE_LDS_8x4x4, PD_SHAPE_GLOBAL_256 = -1, 0, 1, 2, 3
+PD_N_SHAPES = 4
 
 
 class PdError(RuntimeError):
@@ -66,6 +68,8 @@ SIGNATURES = {
     "pd_run_state": [_vp, _vp, _vp],
     "pd_free_run": [_vp],
     "pd_run_batch": [_P(pd_batch_item), _i32, _vp],
+    "pd_autotune": [_vp, _P(pd_params), _i64, _vp, _P(_i32), _vp],
+    "pd_set_launch_shape": [_vp, _i32],
     "pd_qoi_grad": [_vp, _P(pd_params), _vp, _vp, _vp, _vp, _P(_d), _P(_i64), _vp],
     "pd_kl_build": [_vp, _d, _i32, _i32, _P(_vp)],
     "pd_kl_eigenvalues": [_vp, _vp],
@@ -121,6 +125,8 @@ pd_qoi = _wrap("pd_qoi")
 pd_run_state = _wrap("pd_run_state")
 pd_free_run = _wrap("pd_free_run")
 pd_run_batch = _wrap("pd_run_batch")
+pd_autotune = _wrap("pd_autotune")
+pd_set_launch_shape = _wrap("pd_set_launch_shape")
 pd_qoi_grad = _wrap("pd_qoi_grad")
 pd_kl_build = _wrap("pd_kl_build")
 pd_kl_eigenvalues = _wrap("pd_kl_eigenvalues")

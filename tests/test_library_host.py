@@ -99,3 +99,18 @@ def test_null_arguments_are_rejected():
     assert pd.lib().pd_build_mesh(None, None) == pd.PD_EINVAL
     assert pd.lib().pd_run(None, None, None, None) == pd.PD_EINVAL
     assert pd.lib().pd_level_stats(None, None, 0, None, None) == pd.PD_EINVAL
+
+
+def test_launch_shape_pinning_is_validated():
+    rc, h = build(W.level(0).beam, W.level(0).dx)
+    assert rc == pd.PD_OK
+    try:
+        for shape in (pd.PD_SHAPE_AUTO, pd.PD_SHAPE_LDS_16x4x4, pd.PD_SHAPE_GLOBAL_256, pd.PD_N_SHAPES - 1):
+            assert pd.lib().pd_set_launch_shape(h, shape) == pd.PD_OK
+        for bad in (-2, pd.PD_N_SHAPES, 99):
+            assert pd.lib().pd_set_launch_shape(h, bad) == pd.PD_EINVAL
+            assert "launch shape" in pd.pd_last_error()
+        assert pd.lib().pd_set_launch_shape(None, 0) == pd.PD_EINVAL
+        assert pd.lib().pd_autotune(None, None, 1, None, None, None) == pd.PD_EINVAL
+    finally:
+        pd.lib().pd_free_mesh(h)
