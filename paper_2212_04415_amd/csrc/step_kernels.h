@@ -266,6 +266,27 @@ __device__ __forceinline__ void pipeline(LoadF &load, CompF &comp, std::integer_
     pipe_step<0, kHalfStencil, D>(ring, load, comp);
 }
 
+// Order in which the fast loop visits the 61 offset pairs: by |v|^2, then by
+// slot, so that bonds of one length are contiguous (their series
+// coefficients and scaled thresholds are shared).
+struct PairOrder {
+    int k[kHalfStencil];
+};
+
+constexpr int half_len2(int k) { return kHalf.v[k].x * kHalf.v[k].x + kHalf.v[k].y * kHalf.v[k].y + kHalf.v[k].z * kHalf.v[k].z; }
+
+constexpr PairOrder make_pair_order()
+{
+    PairOrder o{};
+    int n = 0;
+    for (int l = 1; l <= 9; ++l)
+        for (int k = 0; k < kHalfStencil; ++k)
+            if (half_len2(k) == l) o.k[n++] = k;
+    return o;
+}
+
+constexpr PairOrder kPairOrder = make_pair_order();
+
 template <typename T> struct FastLoad {
     typename Vec4<T>::t a, b;
     T ca, cb;
@@ -304,8 +325,8 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
                                           Acc3<T, KAHAN> &acc, bool &flag, const uint32_t (&skip)[4],
                                           uint32_t (&exc)[4])
 {
-    auto load = [&](auto kc) {
-        constexpr Off v = kHalf.v[decltype(kc)::value];
+    auto load = [&](auto ic) {
+        constexpr Off v = kHalf.v[kPairOrder.k[decltype(ic)::value]];
         FastLoad<T> r;
         r.a = src.template get<v.x, v.y, v.z>();
         r.b = src.template get<-v.x, -v.y, -v.z>();
@@ -318,10 +339,14 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         }
         return r;
     };
-    T hi = T(-1), lo = T(1);   // extreme weighted x (FP32) or stretch (FP64) seen
+    // Largest weighted series variable (FP32: num |w|, per bond length) or
+    // stretch (FP64), and largest magnitude, for the plain form's flag.
+    T hi = T(-1), ha = T(0);
+    bool fl = false;
     T pend_x = T(0), pend_y = T(0), pend_z = T(0);   // partial sum of the current group of pairs
-    auto comp_pair = [&](auto kc, const FastLoad<T> &r) {
-        constexpr int K = decltype(kc)::value;
+    auto comp_pair = [&](auto ic, const FastLoad<T> &r) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int K = kPairOrder.k[I];
         constexpr Off v = kHalf.v[K];
         constexpr int V2 = v.x * v.x + v.y * v.y + v.z * v.z;
         T eax, eay, eaz, ebx, eby, ebz, wa, wb;
@@ -329,19 +354,30 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         const T nb = num_c<T, v.x, v.y, v.z, -1>(ui, r.b, ebx, eby, ebz);
         bool exa = false, exb = false;
         if constexpr (sizeof(T) == 4) {
-            const T xa = na * T(0.5 / V2), xb = nb * T(0.5 / V2);
-            const T xwa = xa * fabs(r.a.w), xwb = xb * fabs(r.b.w);
-            constexpr T IV = T(1.0 / kSqrtInt[V2]);
-            constexpr T IV15 = T(-1.5 / kSqrtInt[V2]);
-            constexpr T IV25 = T(2.5 / kSqrtInt[V2]);
-            wa = xwa * fma_(xa, fma_(xa, IV25, IV15), IV);
-            wb = xwb * fma_(xb, fma_(xb, IV25, IV15), IV);
+            // x = h num with h = 1/(2|v|^2), and w = (x/|v|)(1 - 3/2 x + 5/2 x^2)
+            // = num (C1 + num (C2 + num C3)); tests on x compare num |w|
+            // against the bound times 2|v|^2.
+            constexpr double h = 0.5 / V2, L = kSqrtInt[V2];
+            constexpr T C1 = T(h / L), C2 = T(-1.5 * h * h / L), C3 = T(2.5 * h * h * h / L);
+            constexpr T S2 = T(2 * V2);
+            const T nwa = na * fabs(r.a.w), nwb = nb * fabs(r.b.w);
+            wa = nwa * fma_(na, fma_(na, C3, C2), C1);
+            wb = nwb * fma_(nb, fma_(nb, C3, C2), C1);
             if constexpr (MASKED) {
-                exa = (xwa > thr) || (xwa < T(-kSeriesBound));
-                exb = (xwb > thr) || (xwb < T(-kSeriesBound));
+                const T ts = thr * S2;
+                exa = (nwa > ts) || (nwa < T(-kSeriesBound) * S2);
+                exb = (nwb > ts) || (nwb < T(-kSeriesBound) * S2);
             } else {
-                hi = fmax(hi, fmax(xwa, xwb));
-                lo = fmin(lo, fmin(xwa, xwb));
+                constexpr bool gfirst = I == 0 || half_len2(kPairOrder.k[I > 0 ? I - 1 : 0]) != V2;
+                constexpr bool glast = I + 1 == kHalfStencil || half_len2(kPairOrder.k[I + 1 < kHalfStencil ? I + 1 : I]) != V2;
+                if constexpr (gfirst) {
+                    hi = fmax(nwa, nwb);
+                    ha = fmax(fabs(nwa), fabs(nwb));
+                } else {
+                    hi = fmax(fmax(hi, nwa), nwb);
+                    ha = fmax(fmax(ha, fabs(nwa)), fabs(nwb));
+                }
+                if constexpr (glast) fl = fl | (hi > thr * S2) | (ha > T(kSeriesBound) * S2);
             }
         } else {
             T rya, ryb;
@@ -351,7 +387,7 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
                 exa = sa > thr;
                 exb = sb > thr;
             } else {
-                hi = fmax(hi, fmax(sa, sb));
+                hi = fmax(fmax(hi, sa), sb);
             }
             wa = sa * rya;
             wb = sb * ryb;
@@ -376,7 +412,7 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         // are chained into the group's partial sum, and each group of four
         // pairs (eight bonds) enters the compensated accumulator once.
         constexpr int G = 4;
-        constexpr bool first = (K % G == 0);
+        constexpr bool first = (I % G == 0);
         const T dw = wa - wb;
         auto part = [&](auto cc, T ea, T eb, T pend) {
             constexpr int C = decltype(cc)::value;
@@ -387,12 +423,13 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         pend_x = part(std::integral_constant<int, v.x>{}, eax, ebx, pend_x);
         pend_y = part(std::integral_constant<int, v.y>{}, eay, eby, pend_y);
         pend_z = part(std::integral_constant<int, v.z>{}, eaz, ebz, pend_z);
-        if constexpr (K % G == G - 1 || K + 1 == kHalfStencil) acc.add(pend_x, pend_y, pend_z);
+        if constexpr (I % G == G - 1 || I + 1 == kHalfStencil) acc.add(pend_x, pend_y, pend_z);
     };
     constexpr int D = sizeof(T) == 4 ? PD_PIPE_DEPTH : 2;
     pipeline<D, FastLoad<T>>(load, comp_pair, std::make_integer_sequence<int, D>{});
     if constexpr (MASKED) flag = false;
-    else if constexpr (sizeof(T) == 4) flag = (hi > thr) || (lo < T(-kSeriesBound));
+    // thr <= 2^-10, so this flags exactly the bonds the masked form excepts
+    else if constexpr (sizeof(T) == 4) flag = fl;
     else flag = hi > thr;
 }
 
