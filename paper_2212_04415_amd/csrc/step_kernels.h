@@ -39,13 +39,16 @@ namespace pdmi {
 constexpr int kXcds = 8;
 
 // Brick of nodes owned by one block (one thread per node, x fastest) and, on
-// the LDS path, its tile with the kHalo-wide halo.  The global path uses the
-// thread count only (a tile is N consecutive nodes).
-template <int BX_, int BY_, int BZ_>
+// the LDS path, its tile with the kHalo-wide halo, rows padded by PADX cells.
+// The global path uses the thread count only (a tile is N consecutive nodes).
+// A 128-bit LDS read serves lanes 0-7 together with lanes 16-23 (and so on),
+// i.e. two rows of a 16-wide brick; a row pitch of 8 (mod 16) cells puts
+// those two rows on disjoint banks.
+template <int BX_, int BY_, int BZ_, int PADX = 0>
 struct Brick {
     static constexpr int BX = BX_, BY = BY_, BZ = BZ_;
     static constexpr int N = BX * BY * BZ;
-    static constexpr int LX = BX + 2 * kHalo, LY = BY + 2 * kHalo, LZ = BZ + 2 * kHalo;
+    static constexpr int LX = BX + 2 * kHalo + PADX, LY = BY + 2 * kHalo, LZ = BZ + 2 * kHalo;
     static constexpr int LXY = LX * LY;
     static constexpr int TILE = LX * LY * LZ;
     static_assert(N % 64 == 0, "a brick is whole wavefronts");
@@ -723,12 +726,13 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         const int bx = (int)(t % a.nbx), by = (int)((t / a.nbx) % a.nby), bz = (int)(t / ((int64_t)a.nbx * a.nby));
         // the tile's first padded cell is the brick origin (node + kHalo - kHalo)
         const int x0 = bx * BR::BX, y0 = by * BR::BY, z0 = bz * BR::BZ;
-        for (int q = threadIdx.x; q < BR::TILE; q += BR::N) {
-            const int lx = q % BR::LX, ly = (q / BR::LX) % BR::LY, lz = q / BR::LXY;
+        constexpr int WX = BR::BX + 2 * kHalo;   // cells per row that hold data
+        for (int q = threadIdx.x; q < WX * BR::LY * BR::LZ; q += BR::N) {
+            const int lx = q % WX, ly = (q / WX) % BR::LY, lz = q / (WX * BR::LY);
             const int px = x0 + lx, py = y0 + ly, pz = z0 + lz;
             V4 v{};
             if (px < a.PX && py < a.PY && pz < a.PZ) v = U[px + (int64_t)py * a.PX + (int64_t)pz * a.PXY];
-            tile[q] = v;
+            tile[lx + BR::LX * ly + BR::LXY * lz] = v;
         }
         __syncthreads();
         const int tx = threadIdx.x % BR::BX, ty = (threadIdx.x / BR::BX) % BR::BY, tz = threadIdx.x / (BR::BX * BR::BY);

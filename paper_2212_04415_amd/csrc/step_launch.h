@@ -17,14 +17,14 @@ static void launch_shape(int shape, dim3 grid, hipStream_t st, const StepParams<
 {
     if constexpr (sizeof(T) == 4 && KAHAN && !HAS_C) {
         switch (shape) {
-        case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4>><<<grid, 256, 0, st>>>(a); return;
+        case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4, 2>><<<grid, 256, 0, st>>>(a); return;
         case PD_SHAPE_LDS_8x8x4: step_kernel<T, KAHAN, HAS_C, true, Brick<8, 8, 4>><<<grid, 256, 0, st>>>(a); return;
         case PD_SHAPE_LDS_8x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<8, 4, 4>><<<grid, 128, 0, st>>>(a); return;
         default: break;
         }
     } else if constexpr (sizeof(T) == 4) {
         if (shape == PD_SHAPE_LDS_16x4x4) {
-            step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4>><<<grid, 256, 0, st>>>(a);
+            step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4, 2>><<<grid, 256, 0, st>>>(a);
             return;
         }
     }
