@@ -58,15 +58,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(per_launch_alg_bytes=None):
+def traffic_from_profiles(kernel):
     """HBM bytes per step-kernel launch from the committed rocprofv3 PMC
-    summary, or None when it is missing or was taken on other kernel source."""
+    summary, or None when it is missing, was taken on other kernel source, or
+    covers another launch shape than the one this run uses."""
     path = os.path.join(ROOT, "profiles", "step_kernel_L1x64_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != "pdmi::" + kernel:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -188,7 +189,8 @@ def main():
     avg_launch_s = gpu_s / launches
     flops_per_launch = 2 * mesh.n_bonds * S * FLOPS_PER_BOND_DIR_F32
     achieved = flops_per_launch / avg_launch_s / 1e12
-    traffic = traffic_from_profiles()
+    kernel = SHAPE_KERNELS[tune["shape"]]
+    traffic = traffic_from_profiles(kernel)
 
     line = {
         "metric": "bond-updates/s and MLMC samples/s on 1 MI355X, batched FP32 vs plain FP64 at equal QoI error",
@@ -211,8 +213,11 @@ def main():
         "time_step_us": avg_launch_s * 1e6,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS_F32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS_F32,
-                     "traffic": traffic, "kernel": SHAPE_KERNELS[tune["shape"]],
+                     "traffic": traffic, "kernel": kernel,
                      "flops_per_launch": flops_per_launch, "avg_launch_us": avg_launch_s * 1e6},
+        "hbm": None if traffic is None else {"bytes_per_launch": traffic,
+                                             "GBps": traffic / avg_launch_s / 1e9,
+                                             "frac_of_8TBps": traffic / avg_launch_s / 8e12},
         "launch_shape": {"chosen": SHAPE_NAMES[tune["shape"]],
                          "autotune_us_per_step": {n: float(t) for n, t in zip(SHAPE_NAMES, tune["us_per_step"])}},
     }
