@@ -119,6 +119,23 @@ def mlmc_leg(fracture=True):
             "load_per_step_mm_L0": levels[0].du * 1e3}
 
 
+def adaptive_leg(eps=80.0, n_warm=100):
+    """Algorithm 1 (adaptive MLMC) on the three cracking-load levels, with the
+    paper's 100 warm-up samples, fitted alpha and RMSE target eps (N)."""
+    import workloads as W
+    from paper_2212_04415_amd import mlmc
+    levels = [W.level(l, fracture=True) for l in range(3)]
+    run, costs, dofs = mlmc.solver_sampler(levels, seed=2, precision="f32", corr_len=W.FIELD_CORR_LEN,
+                                           n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
+                                           kl_coefficients=W.kl_coefficients)
+    out = mlmc.adaptive(run, eps, costs, dofs, n_warm=n_warm, alpha=None, alpha_default=0.5)
+    return {"eps_N": eps, "levels_used": out["L"] + 1, "converged": out["converged"], "N": out["N"],
+            "estimate_N": out["estimate"], "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "bias_estimate_N": out["bias"], "alpha_fitted": out["history"][-1]["alpha"],
+            "wall_s": out["wall_s"], "bond_updates_per_s": out["cost"] / out["wall_s"],
+            "mlmc_samples_per_s": sum(out["N"]) / out["wall_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +145,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain FP64 and cracking-load legs")
     ap.add_argument("--mlmc", action="store_true",
                     help="also run the three-level MLMC hierarchy (1024/128/16 samples + coupled partners)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="also run the adaptive MLMC algorithm on the three levels (RMSE target 80 N)")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="profiling only: time steps per batch solve (default: the workload's 8000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -252,6 +271,8 @@ def main():
 
     if args.mlmc:
         line["mlmc_hierarchy"] = mlmc_leg(fracture=True)
+    if args.adaptive:
+        line["mlmc_adaptive"] = adaptive_leg()
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

@@ -265,6 +265,28 @@ PD_API int pd_level_stats(const double *q_fine_dev, const double *q_coarse_dev, 
  * V_l with 1/(N-1)).  Synchronises stream. */
 PD_API int pd_mlmc_estimate(const double *sums_dev, int32_t n_levels, double *out_host, void *stream);
 
+/* Optimal MLMC sample allocation (paper section 4.3, Eq. sample_allocation):
+ * N_l = eps_s^-2 (sum_k sqrt(V_k C_k)) sqrt(V_l / C_l) for levels 0..n_levels-1,
+ * the minimum-cost allocation whose sampling error sum_l V_l / N_l equals
+ * eps_s^2.  V: level variances (>= 0), C: cost per sample (> 0), host FP64
+ * [n_levels].  n_real_out (nullable): the real-valued N_l; n_out: N_l rounded
+ * down, as in the paper's tables.  Host only. */
+PD_API int pd_mlmc_allocation(const double *V, const double *C, int32_t n_levels, double eps_s, double *n_real_out,
+                              int64_t *n_out);
+
+/* Bias estimate of the finest level (paper section 4.3, Eq. bias_error):
+ * |y_last_mean| / (r refinement^alpha - 1), where refinement is the growth of
+ * the degrees of freedom per level (8 for a 3D lattice when dx halves) and
+ * alpha the weak convergence rate.  Fails with PD_EINVAL unless
+ * r refinement^alpha > 1.  Host only. */
+PD_API int pd_mlmc_bias(double y_last_mean, double alpha, double refinement, double r, double *bias_out);
+
+/* Least-squares fit of log|y| = intercept + slope log x over n >= 2 points
+ * (host FP64 arrays; x > 0, y != 0): the convergence rates of section 4.2
+ * (|E[Y_l]| ~ M_l^-alpha, V[Y_l] ~ M_l^-beta, C_l ~ M_l^gamma) are -slope,
+ * -slope and slope of such fits.  intercept_out is nullable.  Host only. */
+PD_API int pd_mlmc_fit_rate(const double *x, const double *y, int32_t n, double *slope_out, double *intercept_out);
+
 PD_API int pd_free_mesh(pd_mesh m);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -14,7 +14,11 @@ TEST INFRASTRUCTURE ONLY.  Plain NumPy in FP64.
   (Eq. MC_num_samples), both rounded down as in the paper's tables;
 * cost growth exponents 2 + max(0, (gamma - beta)/alpha) for MLMC
   (Eq. MLMC_computational_cost) and 2 + gamma/alpha for standard MC;
-* bias bound |Y_hat_L| / (r m^alpha - 1) (Eq. bias_error).
+* bias bound |Y_hat_L| / (r m^alpha - 1) (Eq. bias_error);
+* convergence rates as least-squares slopes in log-log (section 4.2);
+* the adaptive MLMC algorithm (section 4.3, Algorithm 1), with the garbled
+  line read as "compute N_hat_l - N_l additional samples" and the RMSE budget
+  split evenly: eps_s = eps_b = eps / sqrt(2) (section 4.3, error estimation).
 """
 from __future__ import annotations
 
@@ -72,3 +76,61 @@ def cost_exponents(alpha, beta, gamma):
 
 def bias_bound(y_last, alpha, refinement, r=1.0):
     return abs(y_last) / (r * refinement ** alpha - 1.0)
+
+
+def fit_rate(x, y):
+    """Slope and intercept of the least-squares line log|y| = a + b log x."""
+    lx = np.log(np.asarray(x, dtype=np.float64))
+    ly = np.log(np.abs(np.asarray(y, dtype=np.float64)))
+    b, a = np.polyfit(lx, ly, 1)
+    return float(b), float(a)
+
+
+def adaptive(sampler, eps, costs, dofs, n_warm=100, alpha=None, alpha_default=0.5, refinement=8.0, r=1.0,
+             max_levels=None):
+    """Algorithm 1.  sampler(level, start, count) returns Y for samples
+    start .. start+count-1 of that level (Y_0 = Q_0, Y_l = Q_l - Q_{l-1} on
+    shared random inputs).  costs[l]: cost of one level-l sample; dofs[l]:
+    degrees of freedom M_l (for fitting alpha).  alpha: weak rate for the bias
+    estimate; None fits it from |Y_hat_l|, l >= 1, once two such levels exist,
+    and uses alpha_default before.  Returns the per-level sample counts and
+    sums, the estimate, its sampling variance, the bias estimate and the
+    allocation history."""
+    eps_s = eps_b = eps / np.sqrt(2.0)
+    last = len(costs) - 1 if max_levels is None else max_levels - 1
+    N, Y = [], []
+    history = []
+    L = 0
+    converged = False
+    while True:
+        N.append(0)
+        Y.append(np.zeros(0))
+        # warm-up samples on the new level
+        Y[L] = np.concatenate([Y[L], sampler(L, N[L], n_warm)])
+        N[L] += n_warm
+        # Eq. sample_variance can round below zero when Y barely varies
+        V = [max(level_moments(*level_sums(Y[l]))[1], 0.0) for l in range(L + 1)]
+        _, n_hat = optimal_allocation(V, costs[:L + 1], eps_s)
+        for l in range(L + 1):
+            extra = int(n_hat[l]) - N[l]
+            if extra > 0:
+                Y[l] = np.concatenate([Y[l], sampler(l, N[l], extra)])
+                N[l] += extra
+        means = [level_moments(*level_sums(Y[l]))[0] for l in range(L + 1)]
+        if alpha is not None:
+            a = alpha
+        elif L >= 2:
+            a = -fit_rate(dofs[1:L + 1], means[1:L + 1])[0]
+        else:
+            a = alpha_default
+        bias = bias_bound(means[L], a, refinement, r)
+        history.append(dict(L=L, V=list(V), n_hat=[int(v) for v in n_hat], N=list(N), alpha=a, bias=bias))
+        if bias < eps_b:
+            converged = True
+            break
+        if L == last:
+            break
+        L += 1
+    est, samp, per = mlmc_estimate(Y)
+    return dict(L=L, N=N, sums=[level_sums(y) for y in Y], estimate=est, sampling_variance=samp,
+                bias=history[-1]["bias"], converged=converged, history=history, eps_s=eps_s, eps_b=eps_b)

@@ -174,4 +174,54 @@ int pd_mlmc_estimate(const double *sums_dev, int32_t n_levels, double *out_host,
     return PD_OK;
 }
 
+int pd_mlmc_allocation(const double *V, const double *C, int32_t n_levels, double eps_s, double *n_real_out,
+                       int64_t *n_out)
+{
+    if (!V || !C || !n_out || n_levels < 1) return fail(PD_EINVAL, "bad arguments");
+    if (!(eps_s > 0) || !std::isfinite(eps_s)) return fail(PD_EINVAL, "eps_s must be positive and finite");
+    double sum = 0.0;
+    for (int l = 0; l < n_levels; ++l) {
+        if (!(V[l] >= 0) || !std::isfinite(V[l])) return fail(PD_EINVAL, "level %d: variance must be >= 0", l);
+        if (!(C[l] > 0) || !std::isfinite(C[l])) return fail(PD_EINVAL, "level %d: cost must be > 0", l);
+        sum += std::sqrt(V[l] * C[l]);
+    }
+    const double scale = sum / (eps_s * eps_s);
+    for (int l = 0; l < n_levels; ++l) {
+        const double real = scale * std::sqrt(V[l] / C[l]);          // Eq. sample_allocation
+        if (real > 9.0e18) return fail(PD_EINVAL, "level %d: %g samples do not fit an int64", l, real);
+        if (n_real_out) n_real_out[l] = real;
+        n_out[l] = (int64_t)std::floor(real);
+    }
+    return PD_OK;
+}
+
+int pd_mlmc_bias(double y_last_mean, double alpha, double refinement, double r, double *bias_out)
+{
+    if (!bias_out) return fail(PD_EINVAL, "null output");
+    const double den = r * std::pow(refinement, alpha) - 1.0;         // Eq. bias_error
+    if (!(den > 0) || !std::isfinite(den)) return fail(PD_EINVAL, "r * refinement^alpha must exceed 1");
+    *bias_out = std::fabs(y_last_mean) / den;
+    return PD_OK;
+}
+
+int pd_mlmc_fit_rate(const double *x, const double *y, int32_t n, double *slope_out, double *intercept_out)
+{
+    if (!x || !y || !slope_out || n < 2) return fail(PD_EINVAL, "need at least two points");
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!(x[i] > 0) || !(std::fabs(y[i]) > 0)) return fail(PD_EINVAL, "point %d: x must be > 0 and y nonzero", i);
+        const double lx = std::log(x[i]), ly = std::log(std::fabs(y[i]));
+        sx += lx;
+        sy += ly;
+        sxx += lx * lx;
+        sxy += lx * ly;
+    }
+    const double den = n * sxx - sx * sx;
+    if (!(std::fabs(den) > 0)) return fail(PD_EINVAL, "x values must differ");
+    const double b = (n * sxy - sx * sy) / den;
+    *slope_out = b;
+    if (intercept_out) *intercept_out = (sy - b * sx) / n;
+    return PD_OK;
+}
+
 }  // extern "C"

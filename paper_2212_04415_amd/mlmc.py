@@ -1,4 +1,7 @@
-"""MLMC hierarchy in one batched solve (paper section 4.2).
+"""MLMC drivers (paper section 4): a fixed hierarchy in one batched solve,
+and the adaptive algorithm (section 4.3, Algorithm 1).
+
+Fixed hierarchy (section 4.2).
 
 Level l contributes Y_0 = Q_0 and Y_l = Q_l - Q_{l-1} for l > 0, where both
 terms of a difference are evaluated on the same random input (the same KL
@@ -10,12 +13,14 @@ and the estimator come from pd_level_stats / pd_mlmc_estimate.  Argument
 marshalling only."""
 from __future__ import annotations
 
+import ctypes as C
 import time
-from typing import List, Sequence
+from typing import Callable, Dict, List, Sequence, Tuple
 
 import numpy as np
 
 from . import beam as B
+from . import pd
 
 
 def coupled_batch(levels: Sequence, samples: Sequence[int], seed: int, *, precision: str = "f32",
@@ -58,3 +63,143 @@ def coupled_batch(levels: Sequence, samples: Sequence[int], seed: int, *, precis
                 sampling_variance=est["sampling_variance"], levels=est["levels"], wall_s=wall,
                 bonds=[m.n_bonds for m in meshes], nodes=[m.n_nodes for m in meshes],
                 solves=[o[0].numel() for o in outs], steps=[lv.n_steps for lv in levels])
+
+
+# ---------------------------------------------------------------- adaptive MLMC
+def allocation(V, costs, eps_s):
+    """pd_mlmc_allocation: (real N_l, N_l rounded down)."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    Cs = np.ascontiguousarray(costs, dtype=np.float64)
+    real = np.zeros(V.size)
+    n = np.zeros(V.size, dtype=np.int64)
+    pd.pd_mlmc_allocation(V.ctypes.data, Cs.ctypes.data, V.size, float(eps_s), real.ctypes.data, n.ctypes.data)
+    return real, n
+
+
+def bias(y_last_mean, alpha, refinement=8.0, r=1.0):
+    out = C.c_double()
+    pd.pd_mlmc_bias(float(y_last_mean), float(alpha), float(refinement), float(r), C.byref(out))
+    return out.value
+
+
+def fit_rate(x, y):
+    """pd_mlmc_fit_rate: (slope, intercept) of log|y| against log x."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    b, a = C.c_double(), C.c_double()
+    pd.pd_mlmc_fit_rate(x.ctypes.data, y.ctypes.data, x.size, C.byref(b), C.byref(a))
+    return b.value, a.value
+
+
+def solver_sampler(levels: Sequence, seed: int, *, precision: str = "f32", corr_len: float, n_modes: int,
+                   mean: float, cov: float, kl_coefficients, n_quad: int = 256, stream=None):
+    """A sampler for `adaptive` backed by the batched solver: run(requests)
+    with requests {level: (start, count)} runs, in one pd_run_batch call, the
+    level-l samples start .. start+count-1 (KL coefficients of stream l) and,
+    for l > 0, their coarse partners on the level l-1 mesh with the same
+    coefficients, and returns {level: (q_fine, q_coarse or None)} as device
+    FP64 tensors.  Also returns the per-sample costs (bond updates, fine plus
+    coarse) and the node counts."""
+    import torch
+    meshes = [B.Mesh.for_level(lv) for lv in levels]
+    kls = [B.KL(m, corr_len, n_modes, n_quad) for m in meshes]
+    dtype = torch.float32 if precision == "f32" else torch.float64
+    params = [B.make_params(lv, precision=precision) for lv in levels]
+    work = [m.n_bonds * lv.n_steps for m, lv in zip(meshes, levels)]
+    costs = [work[l] + (work[l - 1] if l > 0 else 0) for l in range(len(levels))]
+    dofs = [3 * m.n_nodes for m in meshes]
+
+    def run(requests: Dict[int, Tuple[int, int]]):
+        items, owners = [], []
+        for l, (start, count) in sorted(requests.items()):
+            xi = torch.tensor(kl_coefficients(seed, start + count, n_modes, stream=l)[start:])
+            items.append(B.BatchItem(meshes[l], params[l], count,
+                                     kls[l].lognormal(xi, mean, cov, dtype=dtype, stream=stream)))
+            owners.append((l, "fine"))
+            if l > 0:
+                items.append(B.BatchItem(meshes[l - 1], params[l - 1], count,
+                                         kls[l - 1].lognormal(xi, mean, cov, dtype=dtype, stream=stream)))
+                owners.append((l, "coarse"))
+        outs = B.run_batch(items, stream=stream)
+        res: Dict[int, list] = {}
+        for (l, kind), (Q, ns, st) in zip(owners, outs):
+            if int(st.abs().sum()) != 0:
+                raise RuntimeError(f"level {l}: a sample went non-finite")
+            res.setdefault(l, [None, None])[0 if kind == "fine" else 1] = Q
+        return {l: (v[0], v[1]) for l, v in res.items()}
+
+    return run, costs, dofs
+
+
+def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[float], *, n_warm: int = 100,
+             alpha=None, alpha_default: float = 0.5, refinement: float = 8.0, r: float = 1.0, max_levels=None,
+             stream=None):
+    """Adaptive MLMC, Algorithm 1.  run({level: (start, count)}) returns
+    {level: (q_fine, q_coarse or None)} device FP64 tensors (see
+    solver_sampler); costs[l] is the cost of one level-l sample and dofs[l]
+    its degrees of freedom.  The RMSE budget eps is split evenly between the
+    sampling error (eps_s = eps / sqrt 2, Eq. sampling_error) and the bias
+    (eps_b = eps / sqrt 2, Eq. bias_error).  Per iteration: warm-up samples
+    on the new finest level, level variances (Eq. sample_variance) from the
+    FP64 level sums, the optimal allocation (Eq. sample_allocation, rounded
+    down), the additional samples of every level in one run() call, and the
+    bias estimate of the finest level, with alpha fitted from |Y_hat_l|,
+    l >= 1, when alpha is None and two such levels exist.  Stops when the
+    bias estimate is below eps_b, or at the last level (converged False)."""
+    import torch
+    eps_s = eps_b = eps / np.sqrt(2.0)
+    last = len(costs) - 1 if max_levels is None else max_levels - 1
+    N: List[int] = []
+    sums: List[np.ndarray] = []
+    history = []
+    wall = 0.0
+
+    def take(requests):
+        nonlocal wall
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        got = run({l: (N[l], c) for l, c in requests.items()})
+        for l, (qf, qc) in got.items():
+            s = B.level_stats(qf.contiguous(), None if qc is None else qc.contiguous(), stream=stream)
+            sums[l] += s.cpu().numpy()
+            N[l] += requests[l]
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t
+
+    def moments():
+        dev = torch.tensor(np.stack(sums), dtype=torch.float64, device="cuda")
+        return B.mlmc_estimate(list(dev), stream=stream)
+
+    L = 0
+    converged = False
+    while True:
+        N.append(0)
+        sums.append(np.zeros(3))
+        take({L: n_warm})
+        est = moments()
+        V = [max(lv[1], 0.0) for lv in est["levels"]]   # rounding can push Eq. sample_variance below 0
+        _, n_hat = allocation(V, costs[:L + 1], eps_s)
+        extra = {l: int(n_hat[l]) - N[l] for l in range(L + 1) if int(n_hat[l]) > N[l]}
+        if extra:
+            take(extra)
+            est = moments()
+        means = [lv[0] for lv in est["levels"]]
+        if alpha is not None:
+            a = alpha
+        elif L >= 2:
+            a = -fit_rate(dofs[1:L + 1], means[1:L + 1])[0]
+        else:
+            a = alpha_default
+        b = bias(means[L], a, refinement, r)
+        history.append(dict(L=L, V=list(V), n_hat=[int(v) for v in n_hat], N=list(N), alpha=a, bias=b))
+        if b < eps_b:
+            converged = True
+            break
+        if L == last:
+            break
+        L += 1
+    est = moments()
+    return dict(L=L, N=N, sums=[tuple(x) for x in sums], estimate=est["estimate"],
+                sampling_variance=est["sampling_variance"], levels=est["levels"], bias=history[-1]["bias"],
+                converged=converged, history=history, eps_s=eps_s, eps_b=eps_b, wall_s=wall,
+                cost=float(sum(n * c for n, c in zip(N, costs))))

@@ -77,6 +77,9 @@ SIGNATURES = {
     "pd_kl_free": [_vp],
     "pd_level_stats": [_vp, _vp, _i64, _vp, _vp],
     "pd_mlmc_estimate": [_vp, _i32, _vp, _vp],
+    "pd_mlmc_allocation": [_vp, _vp, _i32, _d, _vp, _vp],
+    "pd_mlmc_bias": [_d, _d, _d, _d, _P(_d)],
+    "pd_mlmc_fit_rate": [_vp, _vp, _i32, _P(_d), _P(_d)],
     "pd_free_mesh": [_vp],
     "pd_last_error": [],
 }
@@ -134,6 +137,9 @@ pd_kl_field = _wrap("pd_kl_field")
 pd_kl_free = _wrap("pd_kl_free")
 pd_level_stats = _wrap("pd_level_stats")
 pd_mlmc_estimate = _wrap("pd_mlmc_estimate")
+pd_mlmc_allocation = _wrap("pd_mlmc_allocation")
+pd_mlmc_bias = _wrap("pd_mlmc_bias")
+pd_mlmc_fit_rate = _wrap("pd_mlmc_fit_rate")
 pd_free_mesh = _wrap("pd_free_mesh")
 
 

@@ -59,3 +59,78 @@ def test_level_statistics_and_estimator(run):
         assert gm == pytest.approx(m, rel=1e-12)
         assert gv == pytest.approx(v, rel=1e-9, abs=1e-9)
         assert gvu == pytest.approx(v * n / (n - 1), rel=1e-9, abs=1e-9)
+
+
+# ------------------------------------------------------------------ adaptive MLMC
+def _toy_q(l, xi):
+    """Analytic level-l "peak load" of a sample: a common part that cancels in
+    the differences, a bias decaying as 8^(-0.45 l) and level noise."""
+    return (1000 + 60 * xi[:, 0] + 400 * 8.0 ** (-0.45 * l) * (1 + 0.3 * xi[:, 1])
+            + 30 * 8.0 ** (-0.5 * l) * xi[:, 2])
+
+
+def _toy_xi(l, start, count):
+    return W.kl_coefficients(5, start + count, 3, stream=l)[start:]
+
+
+@pytest.mark.parametrize("eps", [20.0, 12.0])
+def test_adaptive_driver_makes_the_oracles_decisions(eps):
+    """Algorithm 1 on the GPU driver (FP64 level sums on the device, the
+    allocation / bias / rate fit through the C ABI) against the oracle's
+    driver, both fed the same analytic samples: the same levels, warm-up and
+    additional sample counts, fitted rates, bias estimates and estimate.
+    eps = 20 converges on level 4; eps = 12 stops unconverged at the last
+    level."""
+    import torch
+    from paper_2212_04415_amd import mlmc as PM
+
+    def run(requests):
+        out = {}
+        for l, (start, count) in requests.items():
+            xi = _toy_xi(l, start, count)
+            qf = torch.tensor(_toy_q(l, xi), device="cuda")
+            qc = torch.tensor(_toy_q(l - 1, xi), device="cuda") if l > 0 else None
+            out[l] = (qf, qc)
+        return out
+
+    def sampler(l, start, count):
+        xi = _toy_xi(l, start, count)
+        return _toy_q(l, xi) - (_toy_q(l - 1, xi) if l > 0 else 0.0)
+
+    costs = [8.0 ** l for l in range(5)]
+    dofs = [1000.0 * 8 ** l for l in range(5)]
+    ref = OM.adaptive(sampler, eps, costs, dofs, n_warm=10, alpha=None, alpha_default=0.5)
+    got = PM.adaptive(run, eps, costs, dofs, n_warm=10, alpha=None, alpha_default=0.5)
+    assert got["converged"] == ref["converged"] and got["converged"] == (eps == 20.0)
+    assert got["L"] == ref["L"] == 4
+    assert got["N"] == ref["N"]
+    assert len(got["history"]) == len(ref["history"])
+    for g, r in zip(got["history"], ref["history"]):
+        assert g["n_hat"] == r["n_hat"] and g["N"] == r["N"]
+        assert g["alpha"] == pytest.approx(r["alpha"], rel=1e-10)
+        assert g["bias"] == pytest.approx(r["bias"], rel=1e-10)
+        assert np.allclose(g["V"], r["V"], rtol=1e-10)
+    assert got["estimate"] == pytest.approx(ref["estimate"], rel=1e-13)
+    assert got["sampling_variance"] == pytest.approx(ref["sampling_variance"], rel=1e-10)
+
+
+def test_adaptive_with_the_solver_reproduces_the_fixed_hierarchy():
+    """Algorithm 1 driving the batched solver on two small cracking-load
+    levels: its samples are the fixed hierarchy's samples 0 .. N_l - 1 (same
+    KL streams), so running the fixed hierarchy with the adaptive counts gives
+    the same level sums and estimate; every level ends with at least its
+    allocation."""
+    from paper_2212_04415_amd import mlmc as PM
+    levels = [W.level(0, fracture=True, steps_scale=0.6), W.level(1, fracture=True, steps_scale=0.6)]
+    kw = dict(precision="f32", corr_len=W.FIELD_CORR_LEN, n_modes=W.FIELD_MODES, mean=W.S0_MEAN,
+              cov=W.FIELD_COV, kl_coefficients=W.kl_coefficients)
+    run, costs, dofs = PM.solver_sampler(levels, seed=3, **kw)
+    out = PM.adaptive(run, 60.0, costs, dofs, n_warm=6, alpha=0.5)
+    assert out["L"] == 1
+    assert out["N"][0] > 6                       # level 0 took additional samples
+    for h in out["history"]:
+        assert all(n >= nh for n, nh in zip(h["N"], h["n_hat"]))
+    fixed = PM.coupled_batch(levels, out["N"], seed=3, **kw)
+    assert fixed["estimate"] == pytest.approx(out["estimate"], rel=1e-12)
+    for a, b in zip(fixed["sums"], out["sums"]):
+        assert np.allclose(a, b, rtol=1e-12)
