@@ -111,7 +111,15 @@ def mlmc_leg(fracture=True):
                              n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
                              kl_coefficients=W.kl_coefficients)
     bu = sum(b * n * st for b, n, st in zip(out["bonds"], out["solves"], out["steps"]))
+    import torch
+    samples = [1024, 128, 16]
+    fine = [torch.tensor(out["Q"][l][:samples[l]], device="cuda") for l in range(3)]
+    coarse = [None] + [torch.tensor(out["Q"][l - 1][samples[l - 1]:samples[l - 1] + samples[l]], device="cuda")
+                       for l in (1, 2)]
+    u = [0.05, 0.5, 0.95]
+    quant = mlmc.cdf(fine, coarse, u)
     return {"wall_s": out["wall_s"], "bond_updates_per_s": bu / out["wall_s"],
+            "multilevel_quantiles_N": {str(k): float(v) for k, v in zip(u, quant)},
             "mlmc_samples_per_s": (1024 + 128 + 16) / out["wall_s"],
             "solves_per_level": out["solves"], "estimate_N": out["estimate"],
             "sampling_std_N": out["sampling_variance"] ** 0.5,

@@ -265,6 +265,22 @@ PD_API int pd_level_stats(const double *q_fine_dev, const double *q_coarse_dev, 
  * V_l with 1/(N-1)).  Synchronises stream. */
 PD_API int pd_mlmc_estimate(const double *sums_dev, int32_t n_levels, double *out_host, void *stream);
 
+/* Multilevel inverse CDF and CDF of the peak load (paper section 7, after
+ * Gregory et al.): with R_l the ascending order statistics of the n_samples[l]
+ * level-l fine samples q_fine_dev[l] and Rc_l those of their coarse partners
+ * q_coarse_dev[l] (the level l-1 solves on the same random inputs; unused for
+ * l = 0),
+ *   F^-1(u) = R_0[ceil(N_0 u)] + sum_{l>=1} (R_l[ceil(N_l u)] - Rc_l[ceil(N_l u)])
+ * (1-based, index clamped to 1..N_l), for each u_host[k] in (0, 1]
+ * -> quantiles_host[k]; and the empirical CDF of those n_u values at the
+ * n_x points x_host -> cdf_host (n_x = 0: skipped).  q_*_dev: host arrays of
+ * n_levels device FP64 pointers (1 <= n_levels <= PD_MAX_CDF_LEVELS).  Ties
+ * are ordered by input position.  Synchronises stream; allocates scratch. */
+enum { PD_MAX_CDF_LEVELS = 8 };
+PD_API int pd_mlmc_cdf(const double *const *q_fine_dev, const double *const *q_coarse_dev, const int64_t *n_samples,
+                       int32_t n_levels, const double *u_host, int64_t n_u, double *quantiles_host,
+                       const double *x_host, int64_t n_x, double *cdf_host, void *stream);
+
 /* Optimal MLMC sample allocation (paper section 4.3, Eq. sample_allocation):
  * N_l = eps_s^-2 (sum_k sqrt(V_k C_k)) sqrt(V_l / C_l) for levels 0..n_levels-1,
  * the minimum-cost allocation whose sampling error sum_l V_l / N_l equals

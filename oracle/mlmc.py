@@ -18,7 +18,10 @@ TEST INFRASTRUCTURE ONLY.  Plain NumPy in FP64.
 * convergence rates as least-squares slopes in log-log (section 4.2);
 * the adaptive MLMC algorithm (section 4.3, Algorithm 1), with the garbled
   line read as "compute N_hat_l - N_l additional samples" and the RMSE budget
-  split evenly: eps_s = eps_b = eps / sqrt(2) (section 4.3, error estimation).
+  split evenly: eps_s = eps_b = eps / sqrt(2) (section 4.3, error estimation);
+* the multilevel inverse CDF and CDF (section 7): order statistics of each
+  level's fine samples minus those of their coarse partners, at index
+  ceil(N_l u), and the empirical CDF of those quantiles.
 """
 from __future__ import annotations
 
@@ -134,3 +137,25 @@ def adaptive(sampler, eps, costs, dofs, n_warm=100, alpha=None, alpha_default=0.
     est, samp, per = mlmc_estimate(Y)
     return dict(L=L, N=N, sums=[level_sums(y) for y in Y], estimate=est, sampling_variance=samp,
                 bias=history[-1]["bias"], converged=converged, history=history, eps_s=eps_s, eps_b=eps_b)
+
+
+def ml_inverse_cdf(fine, coarse, u):
+    """F^-1(u) = R_0[ceil(N_0 u)] + sum_l (R_l[ceil(N_l u)] - Rc_l[ceil(N_l u)]);
+    fine[l]: level-l samples, coarse[l]: their coarse partners (l >= 1)."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.zeros(u.size)
+    for l in range(len(fine)):
+        f = np.sort(np.asarray(fine[l], dtype=np.float64))
+        N = f.size
+        idx = np.clip(np.ceil(N * u).astype(np.int64), 1, N) - 1
+        out += f[idx]
+        if l > 0:
+            c = np.sort(np.asarray(coarse[l], dtype=np.float64))
+            out -= c[idx]
+    return out
+
+
+def ecdf(values, x):
+    """(1/n) #{values <= x} at each x."""
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    return np.searchsorted(v, np.asarray(x, dtype=np.float64), side="right") / v.size

@@ -69,6 +69,64 @@ struct pd_kl_s {
     double *d_sqrt_lam = nullptr;  // [n_modes]
 };
 
+namespace pdmi {
+
+// ---------------------------------------------------------------- multilevel CDF
+static unsigned cdf_blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Order statistics by exact ranking: rank(i) = #{j : q_j < q_i, or q_j = q_i
+// and j < i}, so ties keep their input order and the result is deterministic.
+__global__ void rank_sort_kernel(const double *q, int64_t n, double *sorted)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double qi = q[i];
+    int64_t r = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double qj = q[j];
+        r += (qj < qi) || (qj == qi && j < i);
+    }
+    sorted[r] = qi;
+}
+
+struct CdfLevels {
+    const double *fine[PD_MAX_CDF_LEVELS];
+    const double *coarse[PD_MAX_CDF_LEVELS];
+    int64_t n[PD_MAX_CDF_LEVELS];
+    int n_levels;
+};
+
+// F^-1(u) = R_0[ceil(N_0 u)] + sum_l (R_l[ceil(N_l u)] - Rc_l[ceil(N_l u)]),
+// R sorted fine samples, Rc the sorted coarse partners of level l (1-based
+// order statistics, index clamped to 1..N_l).
+__global__ void ml_quantile_kernel(CdfLevels lv, const double *u, int64_t nu, double *x)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nu) return;
+    double v = 0.0;
+    for (int l = 0; l < lv.n_levels; ++l) {
+        const int64_t N = lv.n[l];
+        int64_t idx = (int64_t)ceil((double)N * u[k]);
+        idx = idx < 1 ? 1 : (idx > N ? N : idx);
+        v += lv.fine[l][idx - 1];
+        if (l > 0) v -= lv.coarse[l][idx - 1];
+    }
+    x[k] = v;
+}
+
+// Empirical CDF of the n values at the query points: #{values <= x} / n.
+__global__ void ecdf_kernel(const double *values, int64_t n, const double *xq, int64_t nx, double *cdf)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nx) return;
+    const double x = xq[m];
+    int64_t c = 0;
+    for (int64_t j = 0; j < n; ++j) c += values[j] <= x;
+    cdf[m] = (double)c / (double)n;
+}
+
+}  // namespace pdmi
+
 extern "C" {
 
 int pd_kl_build(pd_mesh m, double corr_len, int32_t n_modes, int32_t n_quad, pd_kl *out)
@@ -171,6 +229,59 @@ int pd_mlmc_estimate(const double *sums_dev, int32_t n_levels, double *out_host,
     }
     out_host[0] = est;
     out_host[1] = var;
+    return PD_OK;
+}
+
+int pd_mlmc_cdf(const double *const *q_fine_dev, const double *const *q_coarse_dev, const int64_t *n_samples,
+                int32_t n_levels, const double *u_host, int64_t n_u, double *quantiles_host, const double *x_host,
+                int64_t n_x, double *cdf_host, void *stream)
+{
+    if (!q_fine_dev || !n_samples || !u_host || !quantiles_host) return fail(PD_EINVAL, "null argument");
+    if (n_levels < 1 || n_levels > PD_MAX_CDF_LEVELS) return fail(PD_EINVAL, "n_levels must be 1..%d", PD_MAX_CDF_LEVELS);
+    if (n_u < 1) return fail(PD_EINVAL, "n_u must be positive");
+    if (n_x < 0 || (n_x > 0 && (!x_host || !cdf_host))) return fail(PD_EINVAL, "bad CDF query");
+    for (int l = 0; l < n_levels; ++l) {
+        if (n_samples[l] < 1 || n_samples[l] > ((int64_t)1 << 24)) return fail(PD_EINVAL, "level %d: bad sample count", l);
+        if (!q_fine_dev[l] || (l > 0 && (!q_coarse_dev || !q_coarse_dev[l])))
+            return fail(PD_EINVAL, "level %d: missing samples", l);
+    }
+    for (int64_t k = 0; k < n_u; ++k)
+        if (!(u_host[k] > 0.0 && u_host[k] <= 1.0)) return fail(PD_EINVAL, "u[%lld] must lie in (0, 1]", (long long)k);
+    hipStream_t st = (hipStream_t)stream;
+    int64_t total = 0;
+    for (int l = 0; l < n_levels; ++l) total += (l > 0 ? 2 : 1) * n_samples[l];
+    double *buf = nullptr;
+    const size_t bytes = 8 * (size_t)(total + 2 * n_u + 2 * n_x);
+    PD_HIP(hipMalloc(&buf, bytes));
+    CdfLevels lv{};
+    lv.n_levels = n_levels;
+    double *p = buf;
+    for (int l = 0; l < n_levels; ++l) {
+        const int64_t N = n_samples[l];
+        lv.n[l] = N;
+        lv.fine[l] = p;
+        rank_sort_kernel<<<cdf_blocks(N), 256, 0, st>>>(q_fine_dev[l], N, p);
+        p += N;
+        if (l > 0) {
+            lv.coarse[l] = p;
+            rank_sort_kernel<<<cdf_blocks(N), 256, 0, st>>>(q_coarse_dev[l], N, p);
+            p += N;
+        }
+    }
+    double *du = p, *dx = p + n_u, *dq = p + n_u + n_x, *dc = p + 2 * n_u + n_x;
+    hipError_t e = hipMemcpyAsync(du, u_host, 8 * n_u, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && n_x) e = hipMemcpyAsync(dx, x_host, 8 * n_x, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        ml_quantile_kernel<<<cdf_blocks(n_u), 256, 0, st>>>(lv, du, n_u, dq);
+        if (n_x) ecdf_kernel<<<cdf_blocks(n_x), 256, 0, st>>>(dq, n_u, dx, n_x, dc);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(quantiles_host, dq, 8 * n_u, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && n_x) e = hipMemcpyAsync(cdf_host, dc, 8 * n_x, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_fail(e, "pd_mlmc_cdf");
     return PD_OK;
 }
 

@@ -203,3 +203,25 @@ def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[f
                 sampling_variance=est["sampling_variance"], levels=est["levels"], bias=history[-1]["bias"],
                 converged=converged, history=history, eps_s=eps_s, eps_b=eps_b, wall_s=wall,
                 cost=float(sum(n * c for n, c in zip(N, costs))))
+
+
+# ---------------------------------------------------------------- multilevel CDF
+def cdf(q_fine: Sequence, q_coarse: Sequence, u, x=None, stream=None):
+    """pd_mlmc_cdf: multilevel inverse CDF at u (in (0, 1]) and, when x is
+    given, the empirical CDF of those quantiles at x.  q_fine[l] / q_coarse[l]:
+    device FP64 tensors of the level-l fine samples and their coarse partners
+    (q_coarse[0] is ignored)."""
+    L = len(q_fine)
+    fine = (C.c_void_p * L)(*[q.data_ptr() for q in q_fine])
+    coarse = (C.c_void_p * L)(*[None if l == 0 else q_coarse[l].data_ptr() for l in range(L)])
+    n = np.array([q.numel() for q in q_fine], dtype=np.int64)
+    for l in range(1, L):
+        assert q_coarse[l].numel() == n[l]
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    qs = np.zeros(u.size)
+    xs = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+    cs = None if x is None else np.zeros(xs.size)
+    pd.pd_mlmc_cdf(fine, coarse, n.ctypes.data, L, u.ctypes.data, u.size, qs.ctypes.data,
+                   None if xs is None else xs.ctypes.data, 0 if xs is None else xs.size,
+                   None if cs is None else cs.ctypes.data, B._stream_ptr(stream))
+    return (qs, cs) if x is not None else qs

@@ -19,6 +19,7 @@ PD_FIELD_S0, PD_FIELD_C = 0, 1
 PD_DTYPE_F32, PD_DTYPE_F64 = 0, 1
 PD_SHAPE_AUTO, PD_SHAPE_LDS_16x4x4, PD_SHAPE_LDS_8x8x4, PD_SHAPE_LDS_8x4x4, PD_SHAPE_GLOBAL_256 = -1, 0, 1, 2, 3
 PD_N_SHAPES = 4
+PD_MAX_CDF_LEVELS = 8
 
 
 class PdError(RuntimeError):
@@ -77,6 +78,7 @@ SIGNATURES = {
     "pd_kl_free": [_vp],
     "pd_level_stats": [_vp, _vp, _i64, _vp, _vp],
     "pd_mlmc_estimate": [_vp, _i32, _vp, _vp],
+    "pd_mlmc_cdf": [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp],
     "pd_mlmc_allocation": [_vp, _vp, _i32, _d, _vp, _vp],
     "pd_mlmc_bias": [_d, _d, _d, _d, _P(_d)],
     "pd_mlmc_fit_rate": [_vp, _vp, _i32, _P(_d), _P(_d)],
@@ -137,6 +139,7 @@ pd_kl_field = _wrap("pd_kl_field")
 pd_kl_free = _wrap("pd_kl_free")
 pd_level_stats = _wrap("pd_level_stats")
 pd_mlmc_estimate = _wrap("pd_mlmc_estimate")
+pd_mlmc_cdf = _wrap("pd_mlmc_cdf")
 pd_mlmc_allocation = _wrap("pd_mlmc_allocation")
 pd_mlmc_bias = _wrap("pd_mlmc_bias")
 pd_mlmc_fit_rate = _wrap("pd_mlmc_fit_rate")

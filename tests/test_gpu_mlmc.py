@@ -134,3 +134,24 @@ def test_adaptive_with_the_solver_reproduces_the_fixed_hierarchy():
     assert fixed["estimate"] == pytest.approx(out["estimate"], rel=1e-12)
     for a, b in zip(fixed["sums"], out["sums"]):
         assert np.allclose(a, b, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ multilevel CDF
+@pytest.mark.parametrize("sizes", [(1000, 137, 17), (1,), (5, 5), (64, 1, 3)])
+def test_multilevel_cdf_matches_the_oracle(sizes):
+    """pd_mlmc_cdf against the oracle on ragged levels with tied values, at
+    u on a grid, at the smallest u and at u = 1: identical quantiles (same
+    order statistics, same summation order) and identical empirical CDF."""
+    import torch
+    from paper_2212_04415_amd import mlmc as PM
+    rng = np.random.default_rng(len(sizes) * 100 + sizes[0])
+    fine = [np.round(rng.normal(4000 + 200 * l, 300, n), 0) for l, n in enumerate(sizes)]   # ties
+    coarse = [None] + [np.round(f - rng.normal(150, 40, f.size), 0) for f in fine[1:]]
+    u = np.concatenate([np.arange(1, 501) / 500, [1e-12, 1.0, 0.3333333333333333]])
+    x = np.concatenate([np.linspace(3000, 5500, 101), fine[0][:5]])
+    qf = [torch.tensor(f, device="cuda") for f in fine]
+    qc = [None] + [torch.tensor(c, device="cuda") for c in coarse[1:]]
+    qs, cs = PM.cdf(qf, qc, u, x)
+    ref_q = OM.ml_inverse_cdf(fine, coarse, u)
+    assert np.array_equal(qs, ref_q)
+    assert np.array_equal(cs, OM.ecdf(ref_q, x))

@@ -127,3 +127,39 @@ def test_oracle_adaptive_allocation_meets_the_sampling_budget():
     V = [OM.level_moments(*OM.level_sums(pool[l][:out["N"][l]]))[1] for l in range(out["L"] + 1)]
     assert out["sampling_variance"] == pytest.approx(sum(v / n for v, n in zip(V, out["N"])), rel=1e-12)
     assert out["estimate"] == pytest.approx(sum(pool[l][:out["N"][l]].mean() for l in range(out["L"] + 1)), rel=1e-13)
+
+
+# ------------------------------------------------------------------ multilevel CDF (oracle pins)
+def test_single_level_inverse_cdf_is_the_order_statistic():
+    rng = np.random.default_rng(2)
+    X = rng.normal(4000, 300, 37)
+    N = X.size
+    u = np.arange(1, N + 1) / N
+    assert np.array_equal(OM.ml_inverse_cdf([X], [None], u), np.sort(X))
+    # between grid points the next order statistic is taken (ceil)
+    assert np.array_equal(OM.ml_inverse_cdf([X], [None], u - 0.5 / N), np.sort(X))
+    # the CDF of the quantiles on the grid is the plain empirical CDF of the samples
+    xq = np.concatenate([X, X + 1e-9, X - 1e-9, [X.min() - 1, X.max() + 1]])
+    F = OM.ecdf(OM.ml_inverse_cdf([X], [None], u), xq)
+    assert np.array_equal(F, np.array([np.mean(X <= x) for x in xq]))
+
+
+def test_perfectly_coupled_hierarchy_telescopes_to_the_finest_level():
+    """When each level's coarse partners are exactly the level below's fine
+    samples (same count), the corrections cancel and F^-1 is the finest
+    level's empirical quantile function."""
+    rng = np.random.default_rng(3)
+    levels = [rng.normal(4000 + 100 * l, 300, 64) for l in range(4)]
+    u = rng.uniform(1e-6, 1.0, 200)
+    got = OM.ml_inverse_cdf(levels, [None] + levels[:-1], u)
+    assert np.allclose(got, OM.ml_inverse_cdf([levels[-1]], [None], u), rtol=0, atol=1e-9)
+
+
+def test_inverse_cdf_of_uniform_samples_converges():
+    """N = 20000 uniform samples: the empirical quantile stays within the
+    Dvoretzky-Kiefer-Wolfowitz band (eps = sqrt(ln(2/0.001) / 2N)) of u."""
+    rng = np.random.default_rng(4)
+    X = rng.uniform(0.0, 1.0, 20000)
+    u = np.linspace(0.001, 1.0, 999)
+    band = np.sqrt(np.log(2 / 1e-3) / (2 * X.size))
+    assert np.max(np.abs(OM.ml_inverse_cdf([X], [None], u) - u)) < band + 1.0 / X.size
