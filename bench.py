@@ -144,6 +144,39 @@ def adaptive_leg(eps=80.0, n_warm=100):
             "mlmc_samples_per_s": sum(out["N"]) / out["wall_s"]}
 
 
+def sweep_leg(steps=1000):
+    """The size-sweep beams (D = 50 / 100 / 200 / 400 mm, dx = 2.5 mm, 32
+    samples each, seed 4): batched FP32 throughput over the first `steps`
+    time steps of each (the full runs take 8000 D / 50 steps)."""
+    import dataclasses
+    import torch
+    import workloads as W
+    from paper_2212_04415_amd import beam as B
+    sweep = [c for c in W.configs() if c.name == "size_sweep"][0]
+    out = []
+    for i, lv in enumerate(sweep.levels):
+        mesh = B.Mesh.for_level(lv)
+        kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+        S = sweep.samples[i]
+        xi = torch.tensor(W.kl_coefficients(sweep.seed, S, stream=i))
+        s0 = kl.lognormal(xi, W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
+        tune = B.autotune(mesh, B.make_params(lv), S)
+        lvs = dataclasses.replace(lv, n_steps=min(steps, lv.n_steps))
+        item = B.BatchItem(mesh, B.make_params(lvs), S, s0)
+        B.run_batch([dataclasses.replace(item, params=B.make_params(lvs, n_steps=64))])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        B.run_batch([item])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out.append({"depth_mm": round(lv.beam.depth * 1e3), "nodes": mesh.n_nodes, "bonds": mesh.n_bonds,
+                    "samples": S, "steps_timed": lvs.n_steps, "bond_updates_per_s": mesh.n_bonds * lvs.n_steps * S / dt,
+                    "us_per_step": dt / lvs.n_steps * 1e6, "launch_shape": SHAPE_NAMES[tune["shape"]]})
+        del item, s0, kl, mesh
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +188,8 @@ def main():
                     help="also run the three-level MLMC hierarchy (1024/128/16 samples + coupled partners)")
     ap.add_argument("--adaptive", action="store_true",
                     help="also run the adaptive MLMC algorithm on the three levels (RMSE target 80 N)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the size-sweep beams (D = 50..400 mm, 32 samples, first 1000 steps)")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="profiling only: time steps per batch solve (default: the workload's 8000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -281,6 +316,8 @@ def main():
         line["mlmc_hierarchy"] = mlmc_leg(fracture=True)
     if args.adaptive:
         line["mlmc_adaptive"] = adaptive_leg()
+    if args.sweep:
+        line["size_sweep"] = sweep_leg()
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

@@ -1,0 +1,110 @@
+"""GPU parity on the size-sweep beams (geometrically similar notched beams,
+D = 50 / 100 / 200 / 400 mm at dx = 2.5 mm: up to 1.79M nodes and 102M
+bonds), at full size with the sweep's 32 samples per launch.
+
+A solve of these beams is out of the oracle's reach (the D = 400 beam costs
+the oracle about 2 s per time step, and the support reaction stays exactly
+zero until the stress wave reaches the supports after about D / 2 mm steps),
+so the check is one force evaluation of the step kernel on 32 frozen smooth
+fields with per-node limit stretches, compared with the oracle's force at
+sampled nodes: every node next to the notch tip, the pad nodes' corners,
+the box corners and random interior and surface nodes, each evaluated by the
+oracle over that node's own bonds (neighbourhood, notch cut and all)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G
+from oracle import solver as S
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2212_04415_amd import beam
+    return beam
+
+
+def sweep_level(D):
+    return [lv for lv in [c for c in W.configs() if c.name == "size_sweep"][0].levels
+            if abs(lv.beam.depth - D * 1e-3) < 1e-9][0]
+
+
+def sampled_nodes(shape, dx, beam, rng, n_random=96):
+    nx, ny, nz = shape
+    ix = lambda i, j, k: i + nx * (j + ny * k)
+    xn = int(round(0.5 * beam.length / dx))           # first node column right of the notch plane
+    tip = int(round(beam.notch_depth / dx))
+    picks = [ix(i, j, k) for i in range(xn - 3, xn + 3) for j in (0, ny // 2, ny - 1)
+             for k in range(max(tip - 3, 0), min(tip + 3, nz))]
+    sup, load = G.beam_pads(shape, dx, beam)
+    picks += [int(sup[0]), int(sup[-1]), int(load[0]), int(load[-1])]
+    picks += [ix(i, j, k) for i in (0, nx - 1) for j in (0, ny - 1) for k in (0, nz - 1)]
+    picks += list(rng.integers(0, nx * ny * nz, n_random))
+    return np.unique(np.array(picks, dtype=np.int64))
+
+
+def local_problem(lv, shape, node, s0):
+    """The oracle problem of one node's bonds, renumbered: local node 0 is
+    the node, 1.. its neighbours.  Returns the problem and the global ids."""
+    nx, ny, nz = shape
+    i, j, k = node % nx, (node // nx) % ny, node // (nx * ny)
+    st = G.stencil(W.M_RATIO)
+    i2, j2, k2 = i + st[:, 0], j + st[:, 1], k + st[:, 2]
+    ok = (i2 >= 0) & (i2 < nx) & (j2 >= 0) & (j2 < ny) & (k2 >= 0) & (k2 < nz)
+    nb = (i2 + nx * (j2 + ny * k2))[ok]
+    v = st[ok]
+    cut = G.notch_cut_mask(shape, lv.dx, np.minimum(nb, node), np.maximum(nb, node), 0.5 * lv.beam.length,
+                           lv.beam.notch_depth)
+    nb, v = nb[~cut], v[~cut]
+    ids = np.concatenate([[node], nb]).astype(np.int64)
+    n = ids.size
+    delta = W.M_RATIO * lv.dx
+    prob = S.Problem(shape=(n, 1, 1), dx=lv.dx, bond_i=np.zeros(n - 1, dtype=np.int64),
+                     bond_j=np.arange(1, n, dtype=np.int64), xi=v.astype(np.float64) * lv.dx,
+                     support=np.zeros(0, dtype=np.int64), load=np.zeros(0, dtype=np.int64), s0=s0[ids],
+                     c=np.full(n, S.micromodulus(W.E_MODULUS, delta)), rho=W.DENSITY, damping=W.DAMPING,
+                     dt=lv.dt, du=0.0, n_steps=0, law=lv.law, k=W.SOFT_K, alpha=W.SOFT_ALPHA,
+                     GF=W.FRACTURE_ENERGY, delta=delta)
+    return prob, ids
+
+
+@pytest.mark.parametrize("D", [50, 100, 200, 400])
+def test_size_sweep_force_at_full_size(B, D):
+    lv = sweep_level(D)
+    mesh = B.Mesh.for_level(lv)
+    M, shape = mesh.n_nodes, mesh.shape
+    n_samples = 32
+    rng = np.random.default_rng(4000 + D)
+    s0 = W.S0_MEAN * np.exp(0.2 * rng.standard_normal((n_samples, M)))
+    amp = 3e-6                                        # strains up to a few 1e-4 across the 50 mm thickness
+    u = np.stack([W.smooth_displacement(shape, lv.dx, amp, seed=40 + k) for k in (0, n_samples - 1)])
+    u_all = np.empty((n_samples, M, 3))
+    u_all[:] = u[0]
+    u_all[-1] = u[1]
+    u_all = (u_all / lv.dx).astype(np.float32).astype(np.float64) * lv.dx     # as the FP32 state holds it
+    mesh.set_field(0, s0)
+    L = B.force_eval(mesh, B.make_params(lv, precision="f32"), u_all)
+    mesh.set_field(0, None)
+    nodes = sampled_nodes(shape, lv.dx, lv.beam, rng)
+    damaged = 0
+    worst = 0.0
+    for smp in (0, n_samples - 1):
+        for node in nodes:
+            prob, ids = local_problem(lv, shape, int(node), s0[smp])
+            ul = u_all[smp][ids]
+            ref = prob.force(ul)[0]
+            s = prob.stretch(ul)
+            sig = np.sum(np.abs(prob.c[0] * s)) * prob.volume
+            damaged += int(np.sum(s > 0.5 * (prob.s0[0] + prob.s0[1:])))
+            err = np.max(np.abs(L[smp, node] - ref))
+            worst = max(worst, err / (64 * EPS32 * sig))
+            assert err <= 64 * EPS32 * sig, (D, smp, int(node), err, sig)
+    print(f"D = {D} mm: {len(nodes)} nodes x 2 samples, {damaged} bonds past s0, max err / bound = {worst:.3f}")
+    assert damaged > 0
