@@ -51,7 +51,7 @@ enum {
 enum { PD_LAW_EXPLIN = 0, PD_LAW_TRILINEAR = 1 };
 enum { PD_FP32 = 0, PD_FP64 = 1 };
 enum { PD_ACC_KAHAN = 0, PD_ACC_PLAIN = 1 };
-enum { PD_FIELD_S0 = 0, PD_FIELD_C = 1 };
+enum { PD_FIELD_S0 = 0, PD_FIELD_C = 1, PD_FIELD_GF = 2 };
 enum { PD_DTYPE_F32 = 0, PD_DTYPE_F64 = 1 };
 /* Launch shapes of the step kernel: nodes per block as an x-by-y-by-z brick
  * staged with its halo in LDS, or 256 consecutive nodes read through the
@@ -138,12 +138,14 @@ PD_API int pd_mesh_get_info(pd_mesh m, pd_mesh_info_t *info);
 PD_API int pd_mesh_get_pads(pd_mesh m, int32_t *support, int32_t *load);
 
 /* Per-node material field for the single-sample entry points (pd_run,
- * pd_force_eval, pd_qoi_grad).  field: PD_FIELD_S0 (limit stretch) or
- * PD_FIELD_C (micromodulus).  values: [n_samples][n_nodes] of dtype
+ * pd_force_eval).  field: PD_FIELD_S0 (limit stretch), PD_FIELD_C
+ * (micromodulus) or PD_FIELD_GF (fracture energy, N/m; the bond's critical
+ * stretch then follows from the endpoint mean of G_F, appendix A).  values: [n_samples][n_nodes] of dtype
  * PD_DTYPE_F32/F64, on the device if on_device else on the host; the library
  * copies them (async on stream when on_device).  values = NULL clears the
  * field (back to the homogeneous pd_params value).  Bond values are endpoint
- * means (s0_b = (s0_i + s0_j)/2, c_b likewise). */
+ * means (s0_b = (s0_i + s0_j)/2, c_b and G_F,b likewise).  pd_qoi_grad takes
+ * its s0 / c fields as arguments and uses the homogeneous G_F. */
 PD_API int pd_set_material_field(pd_mesh m, int32_t field, int64_t n_samples, const void *values,
                           int32_t on_device, int32_t dtype, void *stream);
 
@@ -181,7 +183,8 @@ PD_API int pd_free_run(pd_run_h r);
  * replayed from a captured HIP graph.  Items whose dt is an integer multiple
  * of the finest dt step on the matching ticks.  Per item: s0 (device,
  * [n_samples][n_nodes], dtype = field_dtype, NULL = homogeneous p->s0),
- * c (device or NULL); outputs qoi (device FP64 [n_samples]), nstar (device
+ * c (micromodulus, device or NULL), gf (fracture energy in N/m, device or
+ * NULL = homogeneous p->GF); outputs qoi (device FP64 [n_samples]), nstar (device
  * int64 [n_samples], nullable), status (device int32 [n_samples], nullable;
  * PD_OK or PD_ENONFINITE).  Async on stream; the caller's buffers must stay
  * valid until it completes.  All items share precision and accumulate. */
@@ -191,6 +194,7 @@ typedef struct {
     int64_t n_samples;
     const void *s0;
     const void *c;
+    const void *gf;
     int32_t field_dtype;
     double *qoi;
     int64_t *nstar;

@@ -49,6 +49,7 @@ typedef struct {
     double GF;                 /* fracture energy */
     double delta;              /* horizon */
     double load_offset;        /* load pad u_z = load_offset - (n+1) du (0 for a fresh run) */
+    const double *gf_node;     /* [n_nodes] fracture energy per node, or NULL: GF everywhere */
 } pdo_problem;
 
 /* ---------------------------------------------------------------- material */
@@ -131,7 +132,8 @@ static void bond_params(const pdo_problem *p, double *c_b, double *s0_b, double 
         int32_t i = p->bond_i[b], j = p->bond_j[b];
         c_b[b] = 0.5 * (p->c_node[i] + p->c_node[j]);
         s0_b[b] = 0.5 * (p->s0_node[i] + p->s0_node[j]);
-        sc_b[b] = pdo_critical_stretch(p->law, s0_b[b], c_b[b], p->GF, p->delta, p->k, p->alpha);
+        double gf_b = p->gf_node ? 0.5 * (p->gf_node[i] + p->gf_node[j]) : p->GF;
+        sc_b[b] = pdo_critical_stretch(p->law, s0_b[b], c_b[b], gf_b, p->delta, p->k, p->alpha);
     }
 }
 

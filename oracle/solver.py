@@ -49,7 +49,7 @@ class _Problem(C.Structure):
         ("volume", C.c_double), ("rho", C.c_double), ("damping", C.c_double),
         ("dt", C.c_double), ("du", C.c_double), ("n_steps", C.c_int64),
         ("law", C.c_int32), ("k", C.c_double), ("alpha", C.c_double),
-        ("GF", C.c_double), ("delta", C.c_double), ("load_offset", C.c_double),
+        ("GF", C.c_double), ("delta", C.c_double), ("load_offset", C.c_double), ("gf_node", C.c_void_p),
     ]
 
 
@@ -130,6 +130,7 @@ class Problem:
     GF: float
     delta: float
     load_offset: float = 0.0
+    gf: object = None          # per-node fracture energy (N/m), or None: GF everywhere
 
     @property
     def n_nodes(self):
@@ -150,10 +151,15 @@ class Problem:
                        self.c.astype(np.float64), self.support.astype(np.int32),
                        self.load.astype(np.int32))]
         bi, bj, xi, s0, c, sup, ld = self._keep
+        gf = None
+        if self.gf is not None:
+            gf = np.ascontiguousarray(np.asarray(self.gf, dtype=np.float64))
+            self._keep.append(gf)
         return _Problem(self.n_nodes, self.n_bonds, _ptr(bi), _ptr(bj), _ptr(xi), _ptr(s0), _ptr(c),
                         sup.size, _ptr(sup), ld.size, _ptr(ld), self.volume, self.rho,
                         self.damping, self.dt, self.du, self.n_steps, self.law, self.k,
-                        self.alpha, self.GF, self.delta, self.load_offset)
+                        self.alpha, self.GF, self.delta, self.load_offset,
+                        None if gf is None else gf.ctypes.data)
 
     def force(self, u, kappa=None):
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.n_nodes, 3)
@@ -201,7 +207,7 @@ class Problem:
 
 
 def beam_problem(level, s0=None, c=None, *, E=None, rho=None, GF=None, damping=None,
-                 k=None, alpha=None, m_ratio=None, n_steps=None, du=None, law=None):
+                 k=None, alpha=None, m_ratio=None, n_steps=None, du=None, law=None, gf=None):
     """Assemble the oracle problem for a workloads.Level.  s0 / c are per-node
     fields (default: homogeneous values)."""
     import workloads as W
@@ -226,4 +232,5 @@ def beam_problem(level, s0=None, c=None, *, E=None, rho=None, GF=None, damping=N
                    support=sup, load=load, s0=s0, c=c, rho=rho, damping=damping,
                    dt=level.dt, du=level.du if du is None else du,
                    n_steps=level.n_steps if n_steps is None else n_steps,
-                   law=level.law if law is None else law, k=k, alpha=alpha, GF=GF, delta=delta)
+                   law=level.law if law is None else law, k=k, alpha=alpha, GF=GF, delta=delta,
+                   gf=None if gf is None else np.asarray(gf, dtype=np.float64))

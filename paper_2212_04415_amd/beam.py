@@ -126,7 +126,8 @@ class BatchItem:
     params: pd.pd_params
     n_samples: int
     s0: object = None          # torch tensor [S][M] on the device, or None
-    c: object = None
+    c: object = None           # micromodulus (absolute), or None
+    gf: object = None          # fracture energy (N/m), or None
 
 
 def run_batch(items: Sequence[BatchItem], stream=None):
@@ -140,16 +141,16 @@ def run_batch(items: Sequence[BatchItem], stream=None):
         ns = torch.empty(it.n_samples, dtype=torch.int64, device=dev)
         st = torch.empty(it.n_samples, dtype=torch.int32, device=dev)
         dtype = pd.PD_DTYPE_F64
-        for f in (it.s0, it.c):
-            if f is not None:
-                assert f.is_cuda and f.is_contiguous() and f.shape == (it.n_samples, it.mesh.n_nodes)
-                dtype = pd.PD_DTYPE_F32 if f.dtype == torch.float32 else pd.PD_DTYPE_F64
-        if it.s0 is not None and it.c is not None:
-            assert it.s0.dtype == it.c.dtype
+        given = [f for f in (it.s0, it.c, it.gf) if f is not None]
+        for f in given:
+            assert f.is_cuda and f.is_contiguous() and f.shape == (it.n_samples, it.mesh.n_nodes)
+            dtype = pd.PD_DTYPE_F32 if f.dtype == torch.float32 else pd.PD_DTYPE_F64
+        assert all(f.dtype == given[0].dtype for f in given)
         keep.append(it.params)
         arr[i] = pd.pd_batch_item(it.mesh.h, C.pointer(it.params), it.n_samples,
                                   it.s0.data_ptr() if it.s0 is not None else None,
-                                  it.c.data_ptr() if it.c is not None else None, dtype,
+                                  it.c.data_ptr() if it.c is not None else None,
+                                  it.gf.data_ptr() if it.gf is not None else None, dtype,
                                   Q.data_ptr(), ns.data_ptr(), st.data_ptr())
         outs.append((Q, ns, st))
     pd.pd_run_batch(arr, len(items), _stream_ptr(stream))

@@ -110,6 +110,8 @@ struct pd_mesh_s {
     int64_t s0_samples = 0;
     double *d_c = nullptr;
     int64_t c_samples = 0;
+    double *d_gf = nullptr;
+    int64_t gf_samples = 0;
 
     int shape_override = -1;   // pinned launch shape (PD_SHAPE_*), -1 = tuned
 

@@ -46,9 +46,9 @@ __global__ void init_state_kernel(typename Vec4<T>::t *u0, typename Vec4<T>::t *
 }
 
 template <typename T, typename In>
-__global__ void fields_kernel(T *s0pad, T *cpad, const In *s0, const In *c, double s0_const,
-                              double inv_cref, int64_t P, int64_t M, int64_t S, int nx, int ny, int nz, int PX,
-                              int64_t PXY, int64_t s0_stride, int64_t c_stride)
+__global__ void fields_kernel(T *s0pad, T *cpad, T *gpad, const In *s0, const In *c, const In *gf, double s0_const,
+                              double inv_cref, double inv_gref, int64_t P, int64_t M, int64_t S, int nx, int ny,
+                              int nz, int PX, int64_t PXY, int64_t s0_stride, int64_t c_stride, int64_t gf_stride)
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P * S) return;
@@ -57,14 +57,16 @@ __global__ void fields_kernel(T *s0pad, T *cpad, const In *s0, const In *c, doub
     int64_t rr = q / PX;
     int j = (int)(rr % (PXY / PX)) - kHalo;
     int k = (int)(rr / (PXY / PX)) - kHalo;
-    T sv = (T)INFINITY, cv = T(0);
+    T sv = (T)INFINITY, cv = T(0), gv = T(0);
     if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) {
         int64_t node = i + (int64_t)nx * (j + (int64_t)ny * k);
         sv = (T)(s0 ? (double)s0[sample * s0_stride + node] : s0_const);
         cv = (T)(c ? (double)c[sample * c_stride + node] * inv_cref : 1.0);
+        gv = (T)(gf ? (double)gf[sample * gf_stride + node] * inv_gref : 1.0);
     }
     s0pad[g] = sv;
     if (cpad) cpad[g] = cv;
+    if (gpad) gpad[g] = gv;
 }
 
 template <typename T>
@@ -111,10 +113,10 @@ static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 // ---------------------------------------------------------------- run buffers
 struct RunBuffers {
     int S = 0;
-    bool f64 = false, kahan = true, has_c = false;
+    bool f64 = false, kahan = true, has_c = false, has_g = false;
     void *u[2] = {nullptr, nullptr};
     void *vh = nullptr, *cu = nullptr, *cvh = nullptr;
-    void *hist = nullptr, *dmask = nullptr, *s0pad = nullptr, *thr = nullptr, *cpad = nullptr;
+    void *hist = nullptr, *dmask = nullptr, *s0pad = nullptr, *thr = nullptr, *cpad = nullptr, *gpad = nullptr;
     double *rf = nullptr, *Q = nullptr, *hist_R = nullptr;
     int64_t *nstar = nullptr, *step = nullptr;
     int32_t *status = nullptr;
@@ -136,7 +138,7 @@ struct RunBuffers {
 };
 
 static int alloc_run(const pd_mesh_s *m, int S, bool f64, bool kahan, bool has_c, bool want_hist_R, int64_t n_steps,
-                     RunBuffers &b, bool outputs)
+                     RunBuffers &b, bool outputs, bool has_g = false)
 {
     b.S = S;
     b.f64 = f64;
@@ -156,6 +158,8 @@ static int alloc_run(const pd_mesh_s *m, int S, bool f64, bool kahan, bool has_c
     if ((rc = b.alloc(&b.s0pad, ts * m->P * S))) return rc;
     if ((rc = b.alloc(&b.thr, ts * m->M * S))) return rc;
     if (has_c && (rc = b.alloc(&b.cpad, ts * m->P * S))) return rc;
+    b.has_g = has_g;
+    if (has_g && (rc = b.alloc(&b.gpad, ts * m->P * S))) return rc;
     if ((rc = b.alloc((void **)&b.rf, 2 * 8 * m->support.size() * S))) return rc;
     if ((rc = b.alloc((void **)&b.step, 8 * S))) return rc;
     if (outputs) {
@@ -219,6 +223,7 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     a.s0pad = (const T *)b.s0pad;
     a.thr = (const T *)b.thr;
     a.cpad = (const T *)b.cpad;
+    a.gpad = (const T *)b.gpad;
     a.info = m->d_info;
     a.cut = m->d_cut;
     a.rf = b.rf;
@@ -290,7 +295,7 @@ static void launch_advance(const Solve &s, int64_t by, hipStream_t st)
 // s0 / c: device [S][M] fields of type In, or null (homogeneous)
 template <typename T, typename In = double>
 static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, int64_t c_stride,
-                       hipStream_t st)
+                       hipStream_t st, const In *gf = nullptr, int64_t gf_stride = 0)
 {
     const pd_mesh_s *m = s.m;
     int64_t S = s.b.S;
@@ -307,8 +312,9 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
     int64_t nh = (int64_t)kStencil * m->M * S;
     fill_kernel<T><<<blocks_for(nh), 256, 0, st>>>((T *)s.b.hist, nh, T(0));
     fill_kernel<uint32_t><<<blocks_for(4 * m->M * S), 256, 0, st>>>((uint32_t *)s.b.dmask, 4 * m->M * S, 0u);
-    fields_kernel<T, In><<<nb, 256, 0, st>>>((T *)s.b.s0pad, (T *)s.b.cpad, s0, c, s.p.s0, 1.0 / s.mat.c_ref, m->P, m->M,
-                                         S, m->nx, m->ny, m->nz, m->PX, (int64_t)m->PX * m->PY, s0_stride, c_stride);
+    fields_kernel<T, In><<<nb, 256, 0, st>>>((T *)s.b.s0pad, (T *)s.b.cpad, (T *)s.b.gpad, s0, c, gf, s.p.s0,
+                                             1.0 / s.mat.c_ref, 1.0 / s.p.GF, m->P, m->M, S, m->nx, m->ny, m->nz,
+                                             m->PX, (int64_t)m->PX * m->PY, s0_stride, c_stride, gf_stride);
     threshold_kernel<T><<<blocks_for(m->M * S), 256, 0, st>>>((T *)s.b.thr, (const T *)s.b.s0pad, m->P, m->M, S,
                                                               m->nx, m->ny, m->PX, (int64_t)m->PX * m->PY);
     init_qoi_kernel<<<blocks_for(S), 256, 0, st>>>(s.b.Q, s.b.nstar, s.b.status, s.b.step, S);
@@ -486,7 +492,8 @@ static int known_shape(const Solve &s)
 // cached choice, else a fresh measurement (after which the solve is set up
 // again from scratch, so the measurement leaves no trace in the results).
 template <typename T, typename In>
-static int choose_shape(Solve &s, const In *s0, int64_t s0_stride, const In *c, int64_t c_stride, hipStream_t st)
+static int choose_shape(Solve &s, const In *s0, int64_t s0_stride, const In *c, int64_t c_stride, hipStream_t st,
+                        const In *gf = nullptr, int64_t gf_stride = 0)
 {
     if (s.b.f64) {
         s.shape = PD_SHAPE_GLOBAL_256;
@@ -513,7 +520,7 @@ static int choose_shape(Solve &s, const In *s0, int64_t s0_stride, const In *c, 
         tune_cache().best[key] = best;
     }
     s.shape = best;
-    return setup_solve<T, In>(s, s0, s0_stride, c, c_stride, st);
+    return setup_solve<T, In>(s, s0, s0_stride, c, c_stride, st, gf, gf_stride);
 }
 
 }  // namespace pdmi

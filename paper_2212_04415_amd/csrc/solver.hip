@@ -124,10 +124,11 @@ int pd_set_material_field(pd_mesh m, int32_t field, int64_t n_samples, const voi
                           int32_t dtype, void *stream)
 {
     if (!m) return fail(PD_EINVAL, "null mesh");
-    if (field != PD_FIELD_S0 && field != PD_FIELD_C) return fail(PD_EINVAL, "unknown field %d", field);
+    if (field != PD_FIELD_S0 && field != PD_FIELD_C && field != PD_FIELD_GF)
+        return fail(PD_EINVAL, "unknown field %d", field);
     if (dtype != PD_DTYPE_F32 && dtype != PD_DTYPE_F64) return fail(PD_EINVAL, "unknown dtype %d", dtype);
-    double **dst = field == PD_FIELD_S0 ? &m->d_s0 : &m->d_c;
-    int64_t *cnt = field == PD_FIELD_S0 ? &m->s0_samples : &m->c_samples;
+    double **dst = field == PD_FIELD_S0 ? &m->d_s0 : field == PD_FIELD_C ? &m->d_c : &m->d_gf;
+    int64_t *cnt = field == PD_FIELD_S0 ? &m->s0_samples : field == PD_FIELD_C ? &m->c_samples : &m->gf_samples;
     if (*dst) {
         (void)hipFree(*dst);
         *dst = nullptr;
@@ -163,6 +164,7 @@ int pd_free_mesh(pd_mesh m)
     if (m->d_support) (void)hipFree(m->d_support);
     if (m->d_s0) (void)hipFree(m->d_s0);
     if (m->d_c) (void)hipFree(m->d_c);
+    if (m->d_gf) (void)hipFree(m->d_gf);
     delete m;
     return PD_OK;
 }
@@ -180,10 +182,13 @@ int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double
     if ((rc = material_from_params(m, p, &s.mat))) return rc;
     if (m->s0_samples && m->s0_samples != n_samples) return fail(PD_EINVAL, "s0 field has %lld samples", (long long)m->s0_samples);
     if (m->c_samples && m->c_samples != n_samples) return fail(PD_EINVAL, "c field has %lld samples", (long long)m->c_samples);
+    if (m->gf_samples && m->gf_samples != n_samples)
+        return fail(PD_EINVAL, "fracture-energy field has %lld samples", (long long)m->gf_samples);
     s.n_steps = 0;
     bool f64 = p->precision == PD_FP64;
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = alloc_run(m, (int)n_samples, f64, p->accumulate == PD_ACC_KAHAN, m->d_c != nullptr, false, 0, s.b, true))) {
+    if ((rc = alloc_run(m, (int)n_samples, f64, p->accumulate == PD_ACC_KAHAN, m->d_c != nullptr, false, 0, s.b, true,
+                        m->d_gf != nullptr))) {
         s.b.release();
         return rc;
     }
@@ -191,8 +196,8 @@ int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double
     std::vector<char> host;
     size_t ts = f64 ? 8 : 4;
     do {
-        if (f64) rc = setup_solve<double>(s, m->d_s0, m->M, m->d_c, m->M, st);
-        else rc = setup_solve<float>(s, m->d_s0, m->M, m->d_c, m->M, st);
+        if (f64) rc = setup_solve<double>(s, m->d_s0, m->M, m->d_c, m->M, st, m->d_gf, m->M);
+        else rc = setup_solve<float>(s, m->d_s0, m->M, m->d_c, m->M, st, m->d_gf, m->M);
         if (rc) break;
         s.shape = known_shape(s);
         // displacements into the padded grid (units of dx), flag 1
@@ -233,7 +238,8 @@ int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out)
     if (!m || !p || !out) return fail(PD_EINVAL, "null argument");
     int rc = ensure_device(m);
     if (rc) return rc;
-    if (m->s0_samples > 1 || m->c_samples > 1) return fail(PD_EINVAL, "pd_run takes single-sample fields");
+    if (m->s0_samples > 1 || m->c_samples > 1 || m->gf_samples > 1)
+        return fail(PD_EINVAL, "pd_run takes single-sample fields");
     pd_run_s *r = new (std::nothrow) pd_run_s();
     if (!r) return fail(PD_ENOMEM, "out of host memory");
     r->s.m = m;
@@ -247,11 +253,11 @@ int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out)
     }
     bool f64 = p->precision == PD_FP64;
     rc = alloc_run(m, 1, f64, p->accumulate == PD_ACC_KAHAN, m->d_c != nullptr, p->record_history != 0, p->n_steps,
-                   r->s.b, true);
-    if (!rc) rc = f64 ? setup_solve<double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream)
-                      : setup_solve<float>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream);
-    if (!rc) rc = f64 ? choose_shape<double, double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream)
-                      : choose_shape<float, double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream);
+                   r->s.b, true, m->d_gf != nullptr);
+    if (!rc) rc = f64 ? setup_solve<double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream, m->d_gf, m->M)
+                      : setup_solve<float>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream, m->d_gf, m->M);
+    if (!rc) rc = f64 ? choose_shape<double, double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream, m->d_gf, m->M)
+                      : choose_shape<float, double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream, m->d_gf, m->M);
     if (!rc) rc = f64 ? enqueue_steps<double>(r->s, r->stream, r->graphs) : enqueue_steps<float>(r->s, r->stream, r->graphs);
     if (rc) {
         (void)hipStreamSynchronize(r->stream);
@@ -409,7 +415,8 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         s.p = *it.params;
         s.n_steps = it.params->n_steps;
         material_from_params(it.mesh, it.params, &s.mat);
-        rc = alloc_run(it.mesh, (int)it.n_samples, f64, kahan, it.c != nullptr, false, s.n_steps, s.b, false);
+        rc = alloc_run(it.mesh, (int)it.n_samples, f64, kahan, it.c != nullptr, false, s.n_steps, s.b, false,
+                       it.gf != nullptr);
         if (rc) break;
         s.b.Q = it.qoi;
         s.b.nstar = (int64_t *)it.nstar;
@@ -419,13 +426,17 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         if (rc) break;
         int64_t M = it.mesh->M;
         if (it.field_dtype == PD_DTYPE_F64) {
-            const double *s0 = (const double *)it.s0, *c = (const double *)it.c;
-            rc = f64 ? setup_solve<double, double>(s, s0, M, c, M, st) : setup_solve<float, double>(s, s0, M, c, M, st);
-            if (!rc) rc = f64 ? choose_shape<double, double>(s, s0, M, c, M, st) : choose_shape<float, double>(s, s0, M, c, M, st);
+            const double *s0 = (const double *)it.s0, *c = (const double *)it.c, *gf = (const double *)it.gf;
+            rc = f64 ? setup_solve<double, double>(s, s0, M, c, M, st, gf, M)
+                     : setup_solve<float, double>(s, s0, M, c, M, st, gf, M);
+            if (!rc) rc = f64 ? choose_shape<double, double>(s, s0, M, c, M, st, gf, M)
+                              : choose_shape<float, double>(s, s0, M, c, M, st, gf, M);
         } else {
-            const float *s0 = (const float *)it.s0, *c = (const float *)it.c;
-            rc = f64 ? setup_solve<double, float>(s, s0, M, c, M, st) : setup_solve<float, float>(s, s0, M, c, M, st);
-            if (!rc) rc = f64 ? choose_shape<double, float>(s, s0, M, c, M, st) : choose_shape<float, float>(s, s0, M, c, M, st);
+            const float *s0 = (const float *)it.s0, *c = (const float *)it.c, *gf = (const float *)it.gf;
+            rc = f64 ? setup_solve<double, float>(s, s0, M, c, M, st, gf, M)
+                     : setup_solve<float, float>(s, s0, M, c, M, st, gf, M);
+            if (!rc) rc = f64 ? choose_shape<double, float>(s, s0, M, c, M, st, gf, M)
+                              : choose_shape<float, float>(s, s0, M, c, M, st, gf, M);
         }
     }
     hipGraphExec_t exec = nullptr;

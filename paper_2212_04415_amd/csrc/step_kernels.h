@@ -85,6 +85,7 @@ struct StepParams {
     const T *s0pad;     // [S][P]
     const T *thr;       // [S][M]
     const T *cpad;      // [S][P] c / c_ref, or null
+    const T *gpad;      // [S][P] fracture energy / its homogeneous value, or null
     const NodeInfo *info;
     const uint4 *cut;
     double *rf;         // [2][S][nsup] support-node force sums, by step parity
@@ -509,7 +510,8 @@ template <typename T, bool KAHAN, bool HAS_C, typename Src>
 __device__ __forceinline__ void exc_loop(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
                                          const T *__restrict__ S0, const T *__restrict__ Cp, T *__restrict__ Hs,
                                          uint32_t lb1, int64_t node, const typename Vec4<T>::t &ui, T s0i, T ci,
-                                         const uint32_t (&todo)[4], uint32_t (&dm)[4], Acc3<T, KAHAN> &acc)
+                                         const T *__restrict__ Gp, T gi, const uint32_t (&todo)[4], uint32_t (&dm)[4],
+                                         Acc3<T, KAHAN> &acc)
 {
     using V4 = typename Vec4<T>::t;
     const uint32_t lbh = (uint32_t)node * (uint32_t)sizeof(T);
@@ -541,7 +543,9 @@ __device__ __forceinline__ void exc_loop(const StepParams<T> &a, const Src &src,
             const T cb = HAS_C ? T(0.5) * (ci + ld(Cp, off, lb1)) : T(1);
             T keep = T(1);
             if (kap > s0b) {
-                const T sc = s0b + quot(a.gamma_rel, cb * s0b);
+                // bond fracture energy: endpoint mean, as for s0 and c
+                const T gb = Gp ? T(0.5) * (gi + ld(Gp, off, lb1)) : T(1);
+                const T sc = s0b + quot(a.gamma_rel * gb, cb * s0b);
                 keep = keep_fraction(a, kap, s0b, sc);
             }
             const T w = keep * s * ry * cb;
@@ -648,7 +652,9 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         const uint32_t todo[4] = {exc[0] & ~cm.x, exc[1] & ~cm.y, exc[2] & ~cm.z, exc[3] & ~cm.w};
         uint32_t dm[4] = {d0.x, d0.y, d0.z, d0.w};
         T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
-        exc_loop<T, KAHAN, HAS_C>(a, src, tab, S0, Cp, Hs, lb1, node, ui, S0[p], ci, todo, dm, acc);
+        const T *__restrict__ Gp = a.gpad ? a.gpad + (int64_t)sample * a.P : nullptr;
+        exc_loop<T, KAHAN, HAS_C>(a, src, tab, S0, Cp, Hs, lb1, node, ui, S0[p], ci, Gp, Gp ? Gp[p] : T(1), todo, dm,
+                                  acc);
         if (dm[0] != d0.x || dm[1] != d0.y || dm[2] != d0.z || dm[3] != d0.w)
             a.dmask[sm] = make_uint4(dm[0], dm[1], dm[2], dm[3]);
         dirty = dirty || ((exc[0] | exc[1] | exc[2] | exc[3]) != 0u);

@@ -15,7 +15,7 @@ PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_EUNSTABLE, PD_ENONFINITE, PD_ESTATE 
 PD_LAW_EXPLIN, PD_LAW_TRILINEAR = 0, 1
 PD_FP32, PD_FP64 = 0, 1
 PD_ACC_KAHAN, PD_ACC_PLAIN = 0, 1
-PD_FIELD_S0, PD_FIELD_C = 0, 1
+PD_FIELD_S0, PD_FIELD_C, PD_FIELD_GF = 0, 1, 2
 PD_DTYPE_F32, PD_DTYPE_F64 = 0, 1
 PD_SHAPE_AUTO, PD_SHAPE_LDS_16x4x4, PD_SHAPE_LDS_8x8x4, PD_SHAPE_LDS_8x4x4, PD_SHAPE_GLOBAL_256 = -1, 0, 1, 2, 3
 PD_N_SHAPES = 4
@@ -49,7 +49,7 @@ class pd_mesh_info_t(C.Structure):
 
 class pd_batch_item(C.Structure):
     _fields_ = [("mesh", C.c_void_p), ("params", C.POINTER(pd_params)), ("n_samples", C.c_int64),
-                ("s0", C.c_void_p), ("c", C.c_void_p), ("field_dtype", C.c_int32),
+                ("s0", C.c_void_p), ("c", C.c_void_p), ("gf", C.c_void_p), ("field_dtype", C.c_int32),
                 ("qoi", C.c_void_p), ("nstar", C.c_void_p), ("status", C.c_void_p)]
 
 
