@@ -255,6 +255,60 @@ PD_API int pd_kl_field(pd_kl kl, const double *xi_dev, int64_t n_samples, double
 
 PD_API int pd_kl_free(pd_kl kl);
 
+/* Covariance families of a KL basis. */
+enum { PD_COV_SQEXP = 0, PD_COV_EXP = 1 };
+
+/* KL basis of the paper's exponential covariance exp(-|x - x'| / corr_len),
+ * unit variance, Euclidean distance (section 5,
+ * Eq. exponential_correlation_function), by Nystrom's method on the mesh's
+ * own node centres with midpoint weights w = dx^3: the largest eigenpairs of
+ * w K from a dense symmetric eigensolver on the device, phi_k(x_j) =
+ * psi_kj / sqrt(w).  Eigenvalues equal to 1e-8 (relative) form a cluster
+ * whose basis is made canonical: the Gram-Schmidt orthonormalisation of the
+ * projections of the probe vectors r_j(i) = cos((i + 1)(j + 1) 0.6180339887498949)
+ * for j = 0, 1, ... (node order i); a single mode thus has <phi, r_0> > 0.
+ * n_modes is extended to the end of a cluster it would split (read the
+ * count with pd_kl_n_modes).  The mesh is the quadrature of every later
+ * pd_kl_extend: build it on the coarsest level.  Limit: n_nodes <= 20000
+ * (dense n^2 matrix).  Synchronous. */
+PD_API int pd_kl_build_exp(pd_mesh m, double corr_len, int32_t n_modes, pd_kl *out);
+
+/* The exponential basis kl evaluated at another mesh's node centres by the
+ * Nystrom extension phi_k(x) = (1 / lambda_k) sum_j w rho(x, x_j) phi_k(x_j),
+ * which reproduces the basis at the quadrature nodes, so every level sees
+ * the same continuous field.  *out is a new handle for `target`.  Fails with
+ * PD_EINVAL for a squared-exponential basis.  Synchronous. */
+PD_API int pd_kl_extend(pd_kl kl, pd_mesh target, pd_kl *out);
+
+PD_API int pd_kl_n_modes(pd_kl kl, int32_t *n_modes_out);
+
+/* Unit-variance Gaussian field g = sum_k sqrt(lambda_k) phi_k xi_k at the
+ * basis' mesh nodes.  xi_dev: device FP64 [n_samples][n_modes]; g_dev: device
+ * FP64 [n_samples][n_nodes].  Async. */
+PD_API int pd_kl_gaussian(pd_kl kl, const double *xi_dev, int64_t n_samples, double *g_dev, void *stream);
+
+/* The paper's material model (section 5 and section 6.2): the compressive
+ * strength has a Weibull marginal of modulus weibull_m and mean fcm through
+ * the Gaussian copula, f_c = lambda (-ln(1 - Phi(g)))^(1/m), lambda = fcm /
+ * Gamma(1 + 1/m); E, f_t and G_F follow from the fib Model Code 2010
+ * relations the paper cites: E = alpha_E 21.5 GPa (f_c / 10 MPa)^(1/3),
+ * f_t = 0.3 MPa (f_ck / MPa)^(2/3) with f_ck = max(f_c - delta_f, fck_min),
+ * G_F = 73 N/m (f_c / MPa)^0.18.  Per node: s0 = f_t / E, c = 12 E / (pi
+ * delta^4) with the mesh's horizon, G_F.  All in SI. */
+typedef struct {
+    double fcm;        /* mean compressive strength, Pa (paper: 42.3e6) */
+    double weibull_m;  /* Weibull modulus (paper: 3) */
+    double alpha_E;    /* aggregate factor of E (1 for quartzite) */
+    double delta_f;    /* f_ck = f_c - delta_f (8e6 Pa) ... */
+    double fck_min;    /* ... but at least fck_min (the relations need f_ck > 0) */
+} pd_fib_params;
+
+/* Per-node limit stretch, micromodulus and fracture energy from a Gaussian
+ * field g_dev (device FP64 [n_samples][n_nodes]) into s0_out, c_out, gf_out
+ * (device [n_samples][n_nodes] of out_dtype; any may be NULL).  Async. */
+PD_API int pd_fib_fields(pd_mesh m, const double *g_dev, int64_t n_samples, const pd_fib_params *fp, void *s0_out,
+                         void *c_out, void *gf_out, int32_t out_dtype, void *stream);
+
 /* FP64 level sums of an MLMC level: Y = q_fine - q_coarse (q_coarse NULL:
  * Y = q_fine), sums_dev[0] = N, [1] = sum Y, [2] = sum Y^2 (device FP64,
  * overwritten).  Deterministic (fixed reduction order).  Async. */

@@ -158,12 +158,40 @@ def run_batch(items: Sequence[BatchItem], stream=None):
 
 
 class KL:
-    """Karhunen-Loeve basis of a mesh (pd_kl_build)."""
+    """Karhunen-Loeve basis of a mesh: squared-exponential (pd_kl_build), or
+    exponential (KL.exponential / extend: pd_kl_build_exp, pd_kl_extend)."""
 
-    def __init__(self, mesh: Mesh, corr_len: float, n_modes: int = 50, n_quad: int = 256):
-        self.mesh, self.n_modes = mesh, n_modes
+    def __init__(self, mesh: Mesh, corr_len: float = None, n_modes: int = 50, n_quad: int = 256, _handle=None):
+        self.mesh = mesh
         self.h = C.c_void_p()
-        pd.pd_kl_build(mesh.h, corr_len, n_modes, n_quad, C.byref(self.h))
+        if _handle is not None:
+            self.h = _handle
+        else:
+            pd.pd_kl_build(mesh.h, corr_len, n_modes, n_quad, C.byref(self.h))
+        n = C.c_int32()
+        pd.pd_kl_n_modes(self.h, C.byref(n))
+        self.n_modes = n.value
+
+    @classmethod
+    def exponential(cls, mesh: Mesh, corr_len: float, n_modes: int = 50):
+        """Nystrom basis of exp(-|x - x'| / corr_len) on this (coarsest) mesh."""
+        h = C.c_void_p()
+        pd.pd_kl_build_exp(mesh.h, corr_len, n_modes, C.byref(h))
+        return cls(mesh, _handle=h)
+
+    def extend(self, target: Mesh):
+        """This exponential basis evaluated at another mesh's nodes."""
+        h = C.c_void_p()
+        pd.pd_kl_extend(self.h, target.h, C.byref(h))
+        return KL(target, _handle=h)
+
+    def gaussian(self, xi, stream=None):
+        """Unit-variance Gaussian field for xi [S][n_modes] (device FP64 out)."""
+        import torch
+        xi = xi.to(device="cuda", dtype=torch.float64).contiguous()
+        out = torch.empty((xi.shape[0], self.mesh.n_nodes), dtype=torch.float64, device="cuda")
+        pd.pd_kl_gaussian(self.h, xi.data_ptr(), xi.shape[0], out.data_ptr(), _stream_ptr(stream))
+        return out
 
     def eigenvalues(self):
         lam = np.zeros(self.n_modes)
@@ -189,6 +217,20 @@ class KL:
             self.close()
         except Exception:
             pass
+
+
+def fib_fields(mesh: Mesh, g, fcm=42.3e6, weibull_m=3.0, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6, dtype=None,
+               stream=None):
+    """pd_fib_fields: per-node (s0, c, G_F) device tensors from a Gaussian
+    field g [S][n_nodes] (device FP64)."""
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    g = g.to(device="cuda", dtype=torch.float64).contiguous()
+    outs = [torch.empty_like(g, dtype=dtype) for _ in range(3)]
+    fp = pd.pd_fib_params(fcm, weibull_m, alpha_E, delta_f, fck_min)
+    pd.pd_fib_fields(mesh.h, g.data_ptr(), g.shape[0], C.byref(fp), *[o.data_ptr() for o in outs],
+                     pd.PD_DTYPE_F64 if dtype == torch.float64 else pd.PD_DTYPE_F32, _stream_ptr(stream))
+    return tuple(outs)
 
 
 def level_stats(q_fine, q_coarse=None, stream=None):

@@ -10,8 +10,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdmi.so")
 
-SOURCES = ["geometry.cpp", "kl.cpp", "solver.hip", "fields.hip", "adjoint.hip", "launch_f32_kahan.hip",
-           "launch_f32_kahan_c.hip", "launch_f32_plain.hip", "launch_f64.hip"]
+SOURCES = ["geometry.cpp", "kl.cpp", "solver.hip", "fields.hip", "adjoint.hip", "material.hip",
+           "launch_f32_kahan.hip", "launch_f32_kahan_c.hip", "launch_f32_plain.hip", "launch_f64.hip"]
+
+# the dense eigensolver of the exponential-covariance KL basis
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -54,7 +57,7 @@ def build(verbose: bool = False) -> str:
             for f in [ex.submit(subprocess.check_call, c) for c in cmds]:
                 f.result()
         tmp = LIB + ".tmp"
-        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
         if verbose:
             print(" ".join(link), flush=True)
         subprocess.check_call(link)

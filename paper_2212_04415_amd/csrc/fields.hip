@@ -61,13 +61,6 @@ __global__ __launch_bounds__(256) void level_sums_kernel(const double *qf, const
 
 using namespace pdmi;
 
-struct pd_kl_s {
-    const pd_mesh_s *mesh = nullptr;
-    int n_modes = 0;
-    std::vector<double> lam;
-    double *d_phi = nullptr;       // [n_modes][M]
-    double *d_sqrt_lam = nullptr;  // [n_modes]
-};
 
 namespace pdmi {
 
@@ -195,6 +188,8 @@ int pd_kl_free(pd_kl kl)
     if (!kl) return PD_OK;
     if (kl->d_phi) (void)hipFree(kl->d_phi);
     if (kl->d_sqrt_lam) (void)hipFree(kl->d_sqrt_lam);
+    if (kl->d_qpos) (void)hipFree(kl->d_qpos);
+    if (kl->d_ext) (void)hipFree(kl->d_ext);
     delete kl;
     return PD_OK;
 }

@@ -121,6 +121,23 @@ struct pd_mesh_s {
     }
 };
 
+// Karhunen-Loeve basis evaluated at a mesh's node centres.  Exponential-
+// covariance bases also keep their Nystrom quadrature (reference node
+// positions and w phi_k(x_j) / lambda_k) so they can be evaluated on other
+// meshes.
+struct pd_kl_s {
+    const pd_mesh_s *mesh = nullptr;
+    int n_modes = 0;
+    int covariance = 0;            // PD_COV_*
+    std::vector<double> lam;
+    double *d_phi = nullptr;       // [n_modes][M]
+    double *d_sqrt_lam = nullptr;  // [n_modes]
+    double corr_len = 0.0;
+    int64_t n_q = 0;               // exponential: quadrature points
+    double *d_qpos = nullptr;      // [n_q][3]
+    double *d_ext = nullptr;       // [n_modes][n_q]
+};
+
 namespace pdmi {
 
 // geometry.cpp

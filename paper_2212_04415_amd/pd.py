@@ -20,6 +20,7 @@ PD_DTYPE_F32, PD_DTYPE_F64 = 0, 1
 PD_SHAPE_AUTO, PD_SHAPE_LDS_16x4x4, PD_SHAPE_LDS_8x8x4, PD_SHAPE_LDS_8x4x4, PD_SHAPE_GLOBAL_256 = -1, 0, 1, 2, 3
 PD_N_SHAPES = 4
 PD_MAX_CDF_LEVELS = 8
+PD_COV_SQEXP, PD_COV_EXP = 0, 1
 
 
 class PdError(RuntimeError):
@@ -45,6 +46,11 @@ class pd_mesh_info_t(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("n_nodes", C.c_int64),
                 ("n_bonds", C.c_int64), ("n_cut", C.c_int64), ("n_support", C.c_int32),
                 ("n_load", C.c_int32), ("n_stencil", C.c_int32), ("delta", C.c_double)]
+
+
+class pd_fib_params(C.Structure):
+    _fields_ = [("fcm", C.c_double), ("weibull_m", C.c_double), ("alpha_E", C.c_double),
+                ("delta_f", C.c_double), ("fck_min", C.c_double)]
 
 
 class pd_batch_item(C.Structure):
@@ -76,6 +82,11 @@ SIGNATURES = {
     "pd_kl_eigenvalues": [_vp, _vp],
     "pd_kl_field": [_vp, _vp, _i64, _d, _d, _vp, _i32, _vp],
     "pd_kl_free": [_vp],
+    "pd_kl_build_exp": [_vp, _d, _i32, _P(_vp)],
+    "pd_kl_extend": [_vp, _vp, _P(_vp)],
+    "pd_kl_n_modes": [_vp, _P(_i32)],
+    "pd_kl_gaussian": [_vp, _vp, _i64, _vp, _vp],
+    "pd_fib_fields": [_vp, _vp, _i64, _P(pd_fib_params), _vp, _vp, _vp, _i32, _vp],
     "pd_level_stats": [_vp, _vp, _i64, _vp, _vp],
     "pd_mlmc_estimate": [_vp, _i32, _vp, _vp],
     "pd_mlmc_cdf": [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp],
@@ -137,6 +148,11 @@ pd_kl_build = _wrap("pd_kl_build")
 pd_kl_eigenvalues = _wrap("pd_kl_eigenvalues")
 pd_kl_field = _wrap("pd_kl_field")
 pd_kl_free = _wrap("pd_kl_free")
+pd_kl_build_exp = _wrap("pd_kl_build_exp")
+pd_kl_extend = _wrap("pd_kl_extend")
+pd_kl_n_modes = _wrap("pd_kl_n_modes")
+pd_kl_gaussian = _wrap("pd_kl_gaussian")
+pd_fib_fields = _wrap("pd_fib_fields")
 pd_level_stats = _wrap("pd_level_stats")
 pd_mlmc_estimate = _wrap("pd_mlmc_estimate")
 pd_mlmc_cdf = _wrap("pd_mlmc_cdf")
