@@ -100,7 +100,7 @@ def cpu_baseline(seconds_target=15.0):
                       f"{dt:.1f} s, single-threaded C at -O2"}
 
 
-def mlmc_leg(fracture=True):
+def mlmc_leg(fracture=True, field_model="lognormal"):
     """The three-level MLMC batch (dx = 5 / 2.5 / 1.25 mm; 1024 / 128 / 16
     samples, each level-l>0 sample paired with a coarse solve on the same KL
     coefficients: 1152 / 144 / 16 solves) in one batched call."""
@@ -109,7 +109,7 @@ def mlmc_leg(fracture=True):
     levels = [W.level(l, fracture=fracture) for l in range(3)]
     out = mlmc.coupled_batch(levels, [1024, 128, 16], seed=2, precision="f32", corr_len=W.FIELD_CORR_LEN,
                              n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
-                             kl_coefficients=W.kl_coefficients)
+                             kl_coefficients=W.kl_coefficients, field_model=field_model)
     bu = sum(b * n * st for b, n, st in zip(out["bonds"], out["solves"], out["steps"]))
     import torch
     samples = [1024, 128, 16]
@@ -186,6 +186,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the plain FP64 and cracking-load legs")
     ap.add_argument("--mlmc", action="store_true",
                     help="also run the three-level MLMC hierarchy (1024/128/16 samples + coupled partners)")
+    ap.add_argument("--mlmc-paper", action="store_true",
+                    help="also run the MLMC hierarchy with the paper's material model (exponential covariance, "
+                         "Weibull strength, fib relations)")
     ap.add_argument("--adaptive", action="store_true",
                     help="also run the adaptive MLMC algorithm on the three levels (RMSE target 80 N)")
     ap.add_argument("--sweep", action="store_true",
@@ -314,6 +317,8 @@ def main():
 
     if args.mlmc:
         line["mlmc_hierarchy"] = mlmc_leg(fracture=True)
+    if args.mlmc_paper:
+        line["mlmc_hierarchy_paper_material"] = mlmc_leg(fracture=True, field_model="paper")
     if args.adaptive:
         line["mlmc_adaptive"] = adaptive_leg()
     if args.sweep:

@@ -25,24 +25,40 @@ from . import pd
 
 def coupled_batch(levels: Sequence, samples: Sequence[int], seed: int, *, precision: str = "f32",
                   corr_len: float, n_modes: int, mean: float, cov: float, kl_coefficients,
-                  n_quad: int = 256, stream=None):
+                  n_quad: int = 256, stream=None, field_model: str = "lognormal"):
     """Runs the hierarchy.  kl_coefficients(seed, n, n_modes, stream) supplies
-    the seeded standard normals; level l uses stream l.  Returns a dict with
-    per-level Y and Q arrays, the estimate, sampling variance, per-level
-    (mean, var, var_unbiased), and the batch's wall time."""
+    the seeded standard normals; level l uses stream l.  field_model
+    "lognormal": lognormal limit stretch (mean, cov) from the separable
+    squared-exponential KL basis of each level; "paper": the exponential-
+    covariance basis of the level-0 mesh extended to every level, mapped to
+    per-node s0, c and fracture energy by the Weibull / fib model (mean and
+    cov unused).  Returns a dict with per-level Y and Q arrays, the estimate,
+    sampling variance, per-level (mean, var, var_unbiased), and the batch's
+    wall time."""
     import torch
     L = len(levels)
     meshes = [B.Mesh.for_level(lv) for lv in levels]
-    kls = [B.KL(m, corr_len, n_modes, n_quad) for m in meshes]
+    if field_model == "lognormal":
+        kls = [B.KL(m, corr_len, n_modes, n_quad) for m in meshes]
+    elif field_model == "paper":
+        base = B.KL.exponential(meshes[0], corr_len, n_modes)
+        kls = [base] + [base.extend(m) for m in meshes[1:]]
+        n_modes = base.n_modes
+    else:
+        raise ValueError(f"unknown field model {field_model!r}")
     xi = [torch.tensor(kl_coefficients(seed, samples[l], n_modes, stream=l)) for l in range(L)]
     dtype = torch.float32 if precision == "f32" else torch.float64
     items, params = [], []
     for l in range(L):
         rows = xi[l] if l + 1 == L else torch.cat([xi[l], xi[l + 1]])
-        s0 = kls[l].lognormal(rows, mean, cov, dtype=dtype, stream=stream)
         p = B.make_params(levels[l], precision=precision)
         params.append(p)
-        items.append(B.BatchItem(meshes[l], p, rows.shape[0], s0))
+        if field_model == "lognormal":
+            s0 = kls[l].lognormal(rows, mean, cov, dtype=dtype, stream=stream)
+            items.append(B.BatchItem(meshes[l], p, rows.shape[0], s0))
+        else:
+            s0, c, gf = B.fib_fields(meshes[l], kls[l].gaussian(rows, stream=stream), dtype=dtype, stream=stream)
+            items.append(B.BatchItem(meshes[l], p, rows.shape[0], s0, c, gf))
     torch.cuda.synchronize()
     t = time.perf_counter()
     outs = B.run_batch(items, stream=stream)
