@@ -38,8 +38,38 @@ def sources():
     return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
+def kernel_resources(remarks: str):
+    """Per-kernel (VGPRs, spilled VGPRs, scratch bytes per lane, occupancy)
+    from the compiler's kernel-resource-usage remarks."""
+    import re
+    out, name = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            out[name] = {}
+            continue
+        m = re.search(r"remark:\s+(VGPRs|VGPRs Spill|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]): (\d+)",
+                      line)
+        if m and name:
+            key = {"VGPRs": "VGPRs", "VGPRs Spill": "VGPRSpill"}.get(m.group(1), m.group(1).split()[0])
+            out[name][key] = int(m.group(2))
+    return out
+
+
+def _compile(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr)
+        raise subprocess.CalledProcessError(r.returncode, cmd)
+    return r.stderr
+
+
 def build(verbose: bool = False) -> str:
-    """Compiles every source to an object in parallel, then links."""
+    """Compiles every source to an object in parallel, then links.  The step
+    kernels' register use is read from the compiler's resource remarks: an
+    FP32 step kernel that spills registers fails the build (it would run
+    several times slower)."""
     from concurrent.futures import ThreadPoolExecutor
     import tempfile
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -49,13 +79,20 @@ def build(verbose: bool = False) -> str:
         for src in sources():
             obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
             objs.append(obj)
-            cmds.append([HIPCC, *compile_flags, *inc, "-c", "-o", obj, src])
+            extra = ["-Rpass-analysis=kernel-resource-usage"] if os.path.basename(src).startswith("launch_") else []
+            cmds.append([HIPCC, *compile_flags, *extra, *inc, "-c", "-o", obj, src])
         if verbose:
             for c in cmds:
                 print(" ".join(c), flush=True)
         with ThreadPoolExecutor(max_workers=min(len(cmds), max(1, os.cpu_count() or 1))) as ex:
-            for f in [ex.submit(subprocess.check_call, c) for c in cmds]:
-                f.result()
+            remarks = "".join(f.result() for f in [ex.submit(_compile, c) for c in cmds])
+        res = {k: v for k, v in kernel_resources(remarks).items() if "step_kernel" in k}
+        spilled = [k for k, v in res.items() if "step_kernelIf" in k and v.get("VGPRSpill", 0) > 0]
+        if verbose:
+            for k, v in sorted(res.items()):
+                print(f"{k}: {v}", flush=True)
+        if spilled:
+            raise RuntimeError("FP32 step kernels spill registers: " + ", ".join(spilled))
         tmp = LIB + ".tmp"
         link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
         if verbose:

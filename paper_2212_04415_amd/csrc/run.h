@@ -159,7 +159,7 @@ static int alloc_run(const pd_mesh_s *m, int S, bool f64, bool kahan, bool has_c
     if ((rc = b.alloc(&b.thr, ts * m->M * S))) return rc;
     if (has_c && (rc = b.alloc(&b.cpad, ts * m->P * S))) return rc;
     b.has_g = has_g;
-    if (has_g && (rc = b.alloc(&b.gpad, ts * m->P * S))) return rc;
+    if ((rc = b.alloc(&b.gpad, has_g ? ts * m->P * S : ts))) return rc;   // without a field: one 1
     if ((rc = b.alloc((void **)&b.rf, 2 * 8 * m->support.size() * S))) return rc;
     if ((rc = b.alloc((void **)&b.step, 8 * S))) return rc;
     if (outputs) {
@@ -224,6 +224,7 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     a.thr = (const T *)b.thr;
     a.cpad = (const T *)b.cpad;
     a.gpad = (const T *)b.gpad;
+    a.gstep = b.has_g ? 1 : 0;
     a.info = m->d_info;
     a.cut = m->d_cut;
     a.rf = b.rf;
@@ -312,7 +313,9 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
     int64_t nh = (int64_t)kStencil * m->M * S;
     fill_kernel<T><<<blocks_for(nh), 256, 0, st>>>((T *)s.b.hist, nh, T(0));
     fill_kernel<uint32_t><<<blocks_for(4 * m->M * S), 256, 0, st>>>((uint32_t *)s.b.dmask, 4 * m->M * S, 0u);
-    fields_kernel<T, In><<<nb, 256, 0, st>>>((T *)s.b.s0pad, (T *)s.b.cpad, (T *)s.b.gpad, s0, c, gf, s.p.s0,
+    if (!s.b.has_g) fill_kernel<T><<<1, 256, 0, st>>>((T *)s.b.gpad, 1, T(1));
+    fields_kernel<T, In><<<nb, 256, 0, st>>>((T *)s.b.s0pad, (T *)s.b.cpad, s.b.has_g ? (T *)s.b.gpad : nullptr, s0, c,
+                                             s.b.has_g ? gf : nullptr, s.p.s0,
                                              1.0 / s.mat.c_ref, 1.0 / s.p.GF, m->P, m->M, S, m->nx, m->ny, m->nz,
                                              m->PX, (int64_t)m->PX * m->PY, s0_stride, c_stride, gf_stride);
     threshold_kernel<T><<<blocks_for(m->M * S), 256, 0, st>>>((T *)s.b.thr, (const T *)s.b.s0pad, m->P, m->M, S,

@@ -85,7 +85,8 @@ struct StepParams {
     const T *s0pad;     // [S][P]
     const T *thr;       // [S][M]
     const T *cpad;      // [S][P] c / c_ref, or null
-    const T *gpad;      // [S][P] fracture energy / its homogeneous value, or null
+    const T *gpad;      // [S][P] fracture energy / its homogeneous value, or one 1 (gstep 0)
+    int gstep;          // 1 with a fracture-energy field, else 0
     const NodeInfo *info;
     const uint4 *cut;
     double *rf;         // [2][S][nsup] support-node force sums, by step parity
@@ -215,13 +216,17 @@ __device__ __forceinline__ E ld(const E *base, int64_t off, uint32_t lane_bytes)
     return *(const E *)((const char *)(base + off) + lane_bytes);
 }
 
-// displacement of the neighbour at lattice offset v, from the padded grid
+// displacement (get) and micromodulus ratio (getc) of the neighbour at
+// lattice offset v, from the padded grids
 template <typename T>
 struct GlobalSrc {
     using V4 = typename Vec4<T>::t;
+    static constexpr bool kLds = false;
     const V4 *U;
     uint32_t lb;
     int64_t PX, PXY;
+    const T *Cp;          // padded c / c_ref of the sample, or null
+    uint32_t lbc;
     template <int X, int Y, int Z> __device__ __forceinline__ V4 get() const
     {
         return ld(U, (int64_t)X + (int64_t)Y * PX + (int64_t)Z * PXY, lb);
@@ -230,19 +235,34 @@ struct GlobalSrc {
     {
         return ld(U, (int64_t)x + (int64_t)y * PX + (int64_t)z * PXY, lb);
     }
+    template <int X, int Y, int Z> __device__ __forceinline__ T getc() const
+    {
+        return ld(Cp, (int64_t)X + (int64_t)Y * PX + (int64_t)Z * PXY, lbc);
+    }
+    __device__ __forceinline__ T getc(int x, int y, int z) const
+    {
+        return ld(Cp, (int64_t)x + (int64_t)y * PX + (int64_t)z * PXY, lbc);
+    }
 };
 
-// ... from the block's LDS tile (brick plus halo)
+// ... from the block's LDS tiles (brick plus halo)
 template <typename T, typename BR>
 struct LdsSrc {
     using V4 = typename Vec4<T>::t;
+    static constexpr bool kLds = true;
     const V4 *tile;
+    const T *ctile;       // c / c_ref tile, or a dummy without a c field
     int c;
     template <int X, int Y, int Z> __device__ __forceinline__ V4 get() const
     {
         return tile[c + X + BR::LX * Y + BR::LXY * Z];
     }
     __device__ __forceinline__ V4 get(int x, int y, int z) const { return tile[c + x + BR::LX * y + BR::LXY * z]; }
+    template <int X, int Y, int Z> __device__ __forceinline__ T getc() const
+    {
+        return ctile[c + X + BR::LX * Y + BR::LXY * Z];
+    }
+    __device__ __forceinline__ T getc(int x, int y, int z) const { return ctile[c + x + BR::LX * y + BR::LXY * z]; }
 };
 
 // ---------------------------------------------------------------- pipelining
@@ -324,8 +344,8 @@ template <typename T> struct FastLoad {
 constexpr double kSeriesBound = 1.0 / 1024;
 
 template <typename T, bool KAHAN, bool HAS_C, bool MASKED, typename Src>
-__device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src, const T *__restrict__ Cp,
-                                          uint32_t lb1, const typename Vec4<T>::t &ui, T ci, T thr,
+__device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src,
+                                          const typename Vec4<T>::t &ui, T ci, T thr,
                                           Acc3<T, KAHAN> &acc, bool &flag, const uint32_t (&skip)[4],
                                           uint32_t (&exc)[4])
 {
@@ -335,9 +355,8 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         r.a = src.template get<v.x, v.y, v.z>();
         r.b = src.template get<-v.x, -v.y, -v.z>();
         if constexpr (HAS_C) {
-            const int64_t off = (int64_t)v.x + (int64_t)v.y * a.PX + (int64_t)v.z * a.PXY;
-            r.ca = ld(Cp, off, lb1);
-            r.cb = ld(Cp, -off, lb1);
+            r.ca = src.template getc<v.x, v.y, v.z>();
+            r.cb = src.template getc<-v.x, -v.y, -v.z>();
         } else {
             r.ca = r.cb = T(1);
         }
@@ -429,7 +448,8 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         pend_z = part(std::integral_constant<int, v.z>{}, eaz, ebz, pend_z);
         if constexpr (I % G == G - 1 || I + 1 == kHalfStencil) acc.add(pend_x, pend_y, pend_z);
     };
-    constexpr int D = sizeof(T) == 4 ? PD_PIPE_DEPTH : 2;
+    // neighbours read through the caches hold more registers in flight
+    constexpr int D = (sizeof(T) == 4 && Src::kLds) ? PD_PIPE_DEPTH : 2;
     pipeline<D, FastLoad<T>>(load, comp_pair, std::make_integer_sequence<int, D>{});
     if constexpr (MASKED) flag = false;
     // thr <= 2^-10, so this flags exactly the bonds the masked form excepts
@@ -508,9 +528,10 @@ __device__ __forceinline__ void fill_slot_lds(SlotLds<T> &t)
 // never passed its limit and has d = 0.  Ghost neighbours contribute nothing.
 template <typename T, bool KAHAN, bool HAS_C, typename Src>
 __device__ __forceinline__ void exc_loop(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
-                                         const T *__restrict__ S0, const T *__restrict__ Cp, T *__restrict__ Hs,
+                                         const T *__restrict__ S0, T *__restrict__ Hs,
                                          uint32_t lb1, int64_t node, const typename Vec4<T>::t &ui, T s0i, T ci,
-                                         const T *__restrict__ Gp, T gi, const uint32_t (&todo)[4], uint32_t (&dm)[4],
+                                         const T *__restrict__ Gp, int gstep, T gi, const uint32_t (&todo)[4],
+                                         uint32_t (&dm)[4],
                                          Acc3<T, KAHAN> &acc)
 {
     using V4 = typename Vec4<T>::t;
@@ -540,11 +561,12 @@ __device__ __forceinline__ void exc_loop(const StepParams<T> &a, const Src &src,
                 *H = s;
                 dm[wd] |= bit;
             }
-            const T cb = HAS_C ? T(0.5) * (ci + ld(Cp, off, lb1)) : T(1);
+            T cb = T(1);
+            if constexpr (HAS_C) cb = T(0.5) * (ci + src.getc(x, y, z));
             T keep = T(1);
             if (kap > s0b) {
                 // bond fracture energy: endpoint mean, as for s0 and c
-                const T gb = Gp ? T(0.5) * (gi + ld(Gp, off, lb1)) : T(1);
+                const T gb = T(0.5) * (gi + ld(Gp, off * gstep, lb1 * (uint32_t)gstep));
                 const T sc = s0b + quot(a.gamma_rel * gb, cb * s0b);
                 keep = keep_fraction(a, kap, s0b, sc);
             }
@@ -634,7 +656,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
             const uint32_t none[4] = {0u, 0u, 0u, 0u};
             uint32_t unused[4] = {0u, 0u, 0u, 0u};
             bool flag = false;
-            fast_loop<T, KAHAN, HAS_C, false>(a, src, Cp, lb1, ui, ci, thr, acc, flag, none, unused);
+            fast_loop<T, KAHAN, HAS_C, false>(a, src, ui, ci, thr, acc, flag, none, unused);
             if (flag) {
                 acc.zero();
                 masked = true;
@@ -648,13 +670,15 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         const uint32_t skip[4] = {cm.x | d0.x, cm.y | d0.y, cm.z | d0.z, cm.w | d0.w};
         uint32_t exc[4] = {0u, 0u, 0u, 0u};
         bool unused = false;
-        fast_loop<T, KAHAN, HAS_C, true>(a, src, Cp, lb1, ui, ci, thr, acc, unused, skip, exc);
+        fast_loop<T, KAHAN, HAS_C, true>(a, src, ui, ci, thr, acc, unused, skip, exc);
         const uint32_t todo[4] = {exc[0] & ~cm.x, exc[1] & ~cm.y, exc[2] & ~cm.z, exc[3] & ~cm.w};
         uint32_t dm[4] = {d0.x, d0.y, d0.z, d0.w};
         T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
-        const T *__restrict__ Gp = a.gpad ? a.gpad + (int64_t)sample * a.P : nullptr;
-        exc_loop<T, KAHAN, HAS_C>(a, src, tab, S0, Cp, Hs, lb1, node, ui, S0[p], ci, Gp, Gp ? Gp[p] : T(1), todo, dm,
-                                  acc);
+        // without a fracture-energy field every bond reads the one unit value
+        const int gstep = a.gstep;
+        const T *__restrict__ Gp = a.gpad + (int64_t)sample * a.P * gstep;
+        exc_loop<T, KAHAN, HAS_C>(a, src, tab, S0, Hs, lb1, node, ui, S0[p], ci, Gp, gstep, ld(Gp, p * gstep, 0u),
+                                  todo, dm, acc);
         if (dm[0] != d0.x || dm[1] != d0.y || dm[2] != d0.z || dm[3] != d0.w)
             a.dmask[sm] = make_uint4(dm[0], dm[1], dm[2], dm[3]);
         dirty = dirty || ((exc[0] | exc[1] | exc[2] | exc[3]) != 0u);
@@ -717,6 +741,7 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
 {
     using V4 = typename Vec4<T>::t;
     __shared__ V4 tile[LDS ? BR::TILE : 1];
+    __shared__ T ctile[(LDS && HAS_C) ? BR::TILE : 1];
     __shared__ SlotLds<T> tab;
     const int64_t per_xcd = gridDim.x / kXcds;
     const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
@@ -736,9 +761,12 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         for (int q = threadIdx.x; q < WX * BR::LY * BR::LZ; q += BR::N) {
             const int lx = q % WX, ly = (q / WX) % BR::LY, lz = q / (WX * BR::LY);
             const int px = x0 + lx, py = y0 + ly, pz = z0 + lz;
+            const bool in = px < a.PX && py < a.PY && pz < a.PZ;
+            const int64_t gi = px + (int64_t)py * a.PX + (int64_t)pz * a.PXY;
             V4 v{};
-            if (px < a.PX && py < a.PY && pz < a.PZ) v = U[px + (int64_t)py * a.PX + (int64_t)pz * a.PXY];
+            if (in) v = U[gi];
             tile[lx + BR::LX * ly + BR::LXY * lz] = v;
+            if constexpr (HAS_C) ctile[lx + BR::LX * ly + BR::LXY * lz] = in ? a.cpad[(int64_t)sample * a.P + gi] : T(0);
         }
         __syncthreads();
         const int tx = threadIdx.x % BR::BX, ty = (threadIdx.x / BR::BX) % BR::BY, tz = threadIdx.x / (BR::BX * BR::BY);
@@ -747,7 +775,7 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         const int64_t node = ix + (int64_t)a.nx * (iy + (int64_t)a.ny * iz);
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
         const int c = (tx + kHalo) + BR::LX * (ty + kHalo) + BR::LXY * (tz + kHalo);
-        const LdsSrc<T, BR> src{tile, c};
+        const LdsSrc<T, BR> src{tile, ctile, c};
         node_step<T, KAHAN, HAS_C>(a, src, tab, sample, n, node, p, tile[c]);
     } else {
         __syncthreads();
@@ -759,7 +787,8 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         const int iz = (int)(r / ny);
         const int iy = (int)(r - (uint32_t)iz * ny);
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
-        const GlobalSrc<T> src{U, (uint32_t)p * (uint32_t)sizeof(V4), a.PX, a.PXY};
+        const GlobalSrc<T> src{U, (uint32_t)p * (uint32_t)sizeof(V4), a.PX, a.PXY,
+                               HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr, (uint32_t)p * (uint32_t)sizeof(T)};
         node_step<T, KAHAN, HAS_C>(a, src, tab, sample, n, node, p, U[p]);
     }
 }
