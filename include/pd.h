@@ -76,7 +76,12 @@ typedef struct pd_kl_s *pd_kl;
  * pad_width x pad_width blocks on the bottom face centred on
  * x = extent[0]/2 -+ span/2; the load pad is one block on the top face centred
  * on x = extent[0]/2; every pad spans the whole thickness.  notch_depth > 0
- * cuts every bond crossing the plane x = extent[0]/2 below that height. */
+ * cuts every bond crossing the plane x = extent[0]/2 below that height.
+ * thickness = 0: a 3D body.  thickness > 0: a plane-stress body of that
+ * thickness (appendix A, Eq. bond_stiffness_constant: c = 9E / (pi t delta^3);
+ * nodal volume dx^2 t; critical stretch from Eq. exp_fracture_energy_2D),
+ * represented with one node through the thickness (extent[1] = dx): every
+ * out-of-plane neighbour is absent, so the 28 in-plane bonds remain. */
 typedef struct {
     double extent[3];
     double dx;
@@ -84,6 +89,7 @@ typedef struct {
     double span;
     double notch_depth;
     double pad_width;
+    double thickness;
 } pd_mesh_desc;
 
 /* Material, loading and numerics of a run.
@@ -261,7 +267,9 @@ enum { PD_COV_SQEXP = 0, PD_COV_EXP = 1 };
 /* KL basis of the paper's exponential covariance exp(-|x - x'| / corr_len),
  * unit variance, Euclidean distance (section 5,
  * Eq. exponential_correlation_function), by Nystrom's method on the mesh's
- * own node centres with midpoint weights w = dx^3: the largest eigenpairs of
+ * own node centres with midpoint weights w = dx^3 (on a plane-stress mesh
+ * the field is 2D: w = dx^2 and the centres are taken on the plane y = 0):
+ * the largest eigenpairs of
  * w K from a dense symmetric eigensolver on the device, phi_k(x_j) =
  * psi_kj / sqrt(w).  Eigenvalues equal to 1e-8 (relative) form a cluster
  * whose basis is made canonical: the Gram-Schmidt orthonormalisation of the
@@ -277,7 +285,8 @@ PD_API int pd_kl_build_exp(pd_mesh m, double corr_len, int32_t n_modes, pd_kl *o
  * Nystrom extension phi_k(x) = (1 / lambda_k) sum_j w rho(x, x_j) phi_k(x_j),
  * which reproduces the basis at the quadrature nodes, so every level sees
  * the same continuous field.  *out is a new handle for `target`.  Fails with
- * PD_EINVAL for a squared-exponential basis.  Synchronous. */
+ * PD_EINVAL for a squared-exponential basis, and when one of the two meshes
+ * is plane-stress and the other 3D.  Synchronous. */
 PD_API int pd_kl_extend(pd_kl kl, pd_mesh target, pd_kl *out);
 
 PD_API int pd_kl_n_modes(pd_kl kl, int32_t *n_modes_out);
@@ -294,7 +303,8 @@ PD_API int pd_kl_gaussian(pd_kl kl, const double *xi_dev, int64_t n_samples, dou
  * relations the paper cites: E = alpha_E 21.5 GPa (f_c / 10 MPa)^(1/3),
  * f_t = 0.3 MPa (f_ck / MPa)^(2/3) with f_ck = max(f_c - delta_f, fck_min),
  * G_F = 73 N/m (f_c / MPa)^0.18.  Per node: s0 = f_t / E, c = 12 E / (pi
- * delta^4) with the mesh's horizon, G_F.  All in SI. */
+ * delta^4) with the mesh's horizon (a plane-stress mesh of thickness t:
+ * c = 9 E / (pi t delta^3), appendix A), G_F.  All in SI. */
 typedef struct {
     double fcm;        /* mean compressive strength, Pa (paper: 42.3e6) */
     double weibull_m;  /* Weibull modulus (paper: 3) */

@@ -23,7 +23,8 @@ TEST INFRASTRUCTURE ONLY.  Plain NumPy / SciPy in FP64.
 * fib Model Code 2010 relations (cited in section 6.2, not printed):
   E = alpha_E 21.5 GPa (f_c / 10 MPa)^(1/3); f_t = 0.3 MPa (f_ck / MPa)^(2/3)
   with f_ck = max(f_c - 8 MPa, f_ck_min); G_F = 73 N/m (f_c / MPa)^0.18;
-  then s0 = f_t / E and c = 12 E / (pi delta^4).
+  then s0 = f_t / E and c = 12 E / (pi delta^4) (plane stress of thickness
+  t: c = 9 E / (pi t delta^3)).
 """
 from __future__ import annotations
 
@@ -139,11 +140,14 @@ def fib_properties(fc, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6):
     return E, ft, GF
 
 
-def material_fields(g, delta, fcm=42.3e6, m=3.0, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6):
-    """Per-node (s0, c, G_F) from a standard-normal Gaussian field g."""
+def material_fields(g, delta, fcm=42.3e6, m=3.0, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6, thickness=0.0):
+    """Per-node (s0, c, G_F) from a standard-normal Gaussian field g; c in
+    the 3D form, or the plane-stress form 9 E / (pi t delta^3) of appendix A
+    (Eq. bond_stiffness_constant) for a body of thickness t > 0."""
     fc = weibull_from_gaussian(g, fcm, m)
     E, ft, GF = fib_properties(fc, alpha_E, delta_f, fck_min)
-    return ft / E, 12.0 * E / (np.pi * delta ** 4), GF
+    c = 9.0 * E / (np.pi * thickness * delta ** 3) if thickness > 0 else 12.0 * E / (np.pi * delta ** 4)
+    return ft / E, c, GF
 
 
 # ---------------------------------------------------------------- 1D closed form (pins)

@@ -50,6 +50,7 @@ typedef struct {
     double delta;              /* horizon */
     double load_offset;        /* load pad u_z = load_offset - (n+1) du (0 for a fresh run) */
     const double *gf_node;     /* [n_nodes] fracture energy per node, or NULL: GF everywhere */
+    double thickness;          /* 0: 3D body; > 0: plane stress of this thickness */
 } pdo_problem;
 
 /* ---------------------------------------------------------------- material */
@@ -75,6 +76,24 @@ double pdo_critical_stretch(int32_t law, double s0, double c, double GF, double 
     }
     /* trilinear: GF = (pi d5 / 5) * 0.2 c s0 (sc - s0) */
     return s0 + GF * 5.0 / (PDO_PI * d5 * 0.2 * c * s0);
+}
+
+/* Critical stretch in plane stress (appendix A, two-dimensional case):
+ * the same bond work integrated over the 2D horizon, Eq. exp_fracture_energy_2D,
+ *   G_F = h c s0 delta^4 (s0 - sc) P / (4 k (e^k - 1)(1 + alpha))   (EXPLIN),
+ *   G_F = (h delta^4 / 2) 0.2 c s0 (sc - s0)                        (TRILINEAR),
+ * solved for sc (the printed Eq. exp_sc_2D is this rearrangement). */
+double pdo_critical_stretch_2d(int32_t law, double s0, double c, double GF, double delta, double h,
+                               double k, double alpha)
+{
+    double d4 = pow(delta, 4.0);
+    if (law == PDO_LAW_EXPLIN) {
+        double ek = exp(k);
+        double P = 2.0 * k - 2.0 * ek + alpha * k - alpha * k * ek + 2.0;
+        double s0_minus_sc = GF * 4.0 * k * (ek - 1.0) * (1.0 + alpha) / (h * c * s0 * d4 * P);
+        return s0 - s0_minus_sc;
+    }
+    return s0 + GF / (0.5 * h * d4 * 0.2 * c * s0);
 }
 
 /* Damage d = D(kappa) for a bond with limit stretch s0 and critical stretch sc
@@ -133,7 +152,9 @@ static void bond_params(const pdo_problem *p, double *c_b, double *s0_b, double 
         c_b[b] = 0.5 * (p->c_node[i] + p->c_node[j]);
         s0_b[b] = 0.5 * (p->s0_node[i] + p->s0_node[j]);
         double gf_b = p->gf_node ? 0.5 * (p->gf_node[i] + p->gf_node[j]) : p->GF;
-        sc_b[b] = pdo_critical_stretch(p->law, s0_b[b], c_b[b], gf_b, p->delta, p->k, p->alpha);
+        sc_b[b] = p->thickness > 0
+                      ? pdo_critical_stretch_2d(p->law, s0_b[b], c_b[b], gf_b, p->delta, p->thickness, p->k, p->alpha)
+                      : pdo_critical_stretch(p->law, s0_b[b], c_b[b], gf_b, p->delta, p->k, p->alpha);
     }
 }
 

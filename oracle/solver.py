@@ -50,6 +50,7 @@ class _Problem(C.Structure):
         ("dt", C.c_double), ("du", C.c_double), ("n_steps", C.c_int64),
         ("law", C.c_int32), ("k", C.c_double), ("alpha", C.c_double),
         ("GF", C.c_double), ("delta", C.c_double), ("load_offset", C.c_double), ("gf_node", C.c_void_p),
+        ("thickness", C.c_double),
     ]
 
 
@@ -66,6 +67,8 @@ def lib():
         d, i64 = C.c_double, C.c_int64
         L.pdo_critical_stretch.restype = d
         L.pdo_critical_stretch.argtypes = [C.c_int32, d, d, d, d, d, d]
+        L.pdo_critical_stretch_2d.restype = d
+        L.pdo_critical_stretch_2d.argtypes = [C.c_int32, d, d, d, d, d, d, d]
         L.pdo_damage.restype = d
         L.pdo_damage.argtypes = [C.c_int32, d, d, d, d, d]
         L.pdo_force.restype = C.c_int
@@ -90,6 +93,15 @@ def micromodulus(E, delta):
 
 def critical_stretch(law, s0, c, GF, delta, k, alpha):
     return lib().pdo_critical_stretch(law, s0, c, GF, delta, k, alpha)
+
+
+def critical_stretch_2d(law, s0, c, GF, delta, h, k, alpha):
+    return lib().pdo_critical_stretch_2d(law, s0, c, GF, delta, h, k, alpha)
+
+
+def micromodulus_plane_stress(E, delta, t):
+    """Appendix A, Eq. bond_stiffness_constant (plane stress)."""
+    return 9.0 * E / (np.pi * t * delta ** 3)
 
 
 def damage(law, kappa, s0, sc, k, alpha):
@@ -131,6 +143,7 @@ class Problem:
     delta: float
     load_offset: float = 0.0
     gf: object = None          # per-node fracture energy (N/m), or None: GF everywhere
+    thickness: float = 0.0     # 0: 3D body; > 0: plane stress of this thickness
 
     @property
     def n_nodes(self):
@@ -142,7 +155,7 @@ class Problem:
 
     @property
     def volume(self):
-        return self.dx ** 3
+        return self.dx ** 3 if self.thickness == 0 else self.dx ** 2 * self.thickness
 
     def _struct(self):
         self._keep = [np.ascontiguousarray(a) for a in
@@ -159,7 +172,7 @@ class Problem:
                         sup.size, _ptr(sup), ld.size, _ptr(ld), self.volume, self.rho,
                         self.damping, self.dt, self.du, self.n_steps, self.law, self.k,
                         self.alpha, self.GF, self.delta, self.load_offset,
-                        None if gf is None else gf.ctypes.data)
+                        None if gf is None else gf.ctypes.data, self.thickness)
 
     def force(self, u, kappa=None):
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.n_nodes, 3)
@@ -219,7 +232,10 @@ def beam_problem(level, s0=None, c=None, *, E=None, rho=None, GF=None, damping=N
     alpha = W.SOFT_ALPHA if alpha is None else alpha
     m_ratio = W.M_RATIO if m_ratio is None else m_ratio
     beam, dx = level.beam, level.dx
-    shape = G.grid_shape((beam.length, beam.thickness, beam.depth), dx)
+    plane = getattr(beam, "plane", False)
+    # a plane-stress body is one node thick; its physical thickness enters
+    # the micromodulus, the nodal volume and the critical stretch
+    shape = G.grid_shape((beam.length, dx if plane else beam.thickness, beam.depth), dx)
     bi, bj, v = G.unique_bonds(shape, m_ratio)
     cut = G.notch_cut_mask(shape, dx, bi, bj, 0.5 * beam.length, beam.notch_depth)
     bi, bj, v = bi[~cut], bj[~cut], v[~cut]
@@ -227,10 +243,12 @@ def beam_problem(level, s0=None, c=None, *, E=None, rho=None, GF=None, damping=N
     M = int(np.prod(shape))
     delta = m_ratio * dx
     s0 = np.full(M, W.S0_MEAN) if s0 is None else np.asarray(s0, dtype=np.float64)
-    c = np.full(M, micromodulus(E, delta)) if c is None else np.asarray(c, dtype=np.float64)
+    c_ref = micromodulus_plane_stress(E, delta, beam.thickness) if plane else micromodulus(E, delta)
+    c = np.full(M, c_ref) if c is None else np.asarray(c, dtype=np.float64)
     return Problem(shape=shape, dx=dx, bond_i=bi, bond_j=bj, xi=v.astype(np.float64) * dx,
                    support=sup, load=load, s0=s0, c=c, rho=rho, damping=damping,
                    dt=level.dt, du=level.du if du is None else du,
                    n_steps=level.n_steps if n_steps is None else n_steps,
                    law=level.law if law is None else law, k=k, alpha=alpha, GF=GF, delta=delta,
-                   gf=None if gf is None else np.asarray(gf, dtype=np.float64))
+                   gf=None if gf is None else np.asarray(gf, dtype=np.float64),
+                   thickness=beam.thickness if plane else 0.0)

@@ -23,8 +23,10 @@ class Mesh:
 
     def __init__(self, beam, dx: float, m_ratio: float = 3.14):
         self.beam, self.dx = beam, dx
-        desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, beam.thickness, beam.depth), dx, m_ratio,
-                               beam.span, beam.notch_depth, beam.pad_width)
+        plane = getattr(beam, "plane", False)
+        desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, dx if plane else beam.thickness, beam.depth), dx,
+                               m_ratio, beam.span, beam.notch_depth, beam.pad_width,
+                               beam.thickness if plane else 0.0)
         self.h = C.c_void_p()
         pd.pd_build_mesh(C.byref(desc), C.byref(self.h))
         nb = C.c_int64()

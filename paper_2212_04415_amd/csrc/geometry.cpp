@@ -45,11 +45,13 @@ static long whole(double len, double unit)
     return k;
 }
 
-double stencil_inv_len_sum()
+// sum over the horizon of 1/|v|; in_plane: the offsets with v_y = 0 only
+double stencil_inv_len_sum(bool in_plane)
 {
     double s = 0.0;
     for (int k = 0; k < kHalfStencil; ++k) {
         Off o = kHalf.v[k];
+        if (in_plane && o.y != 0) continue;
         s += 2.0 / std::sqrt((double)(o.x * o.x + o.y * o.y + o.z * o.z));
     }
     return s;
@@ -57,10 +59,12 @@ double stencil_inv_len_sum()
 
 // Explicit stability limit of an interior node (Silling and Askari's bound
 // for bond-based peridynamics): dt_c = sqrt(2 rho / sum_j V c / |xi_j|).
-double stability_limit(double rho, double c, double dx)
+double stability_limit(const pd_mesh_s *m, double rho, double c)
 {
-    double V = dx * dx * dx;
-    return std::sqrt(2.0 * rho / (V * c * stencil_inv_len_sum() / dx));
+    const double dx = m->d.dx;
+    const bool plane = m->d.thickness > 0;
+    const double V = plane ? dx * dx * m->d.thickness : dx * dx * dx;
+    return std::sqrt(2.0 * rho / (V * c * stencil_inv_len_sum(plane) / dx));
 }
 
 int build_mesh(const pd_mesh_desc *d, pd_mesh_s *m)
@@ -75,6 +79,9 @@ int build_mesh(const pd_mesh_desc *d, pd_mesh_s *m)
         if (n[a] < 1) return fail(PD_EINVAL, "extent[%d] = %g is not a positive multiple of dx", a, d->extent[a]);
     }
     if ((double)n[0] * n[1] * n[2] > 2.0e9) return fail(PD_EINVAL, "mesh too large");
+    if (!(d->thickness >= 0)) return fail(PD_EINVAL, "thickness must be >= 0");
+    if (d->thickness > 0 && n[1] != 1)
+        return fail(PD_EINVAL, "a plane-stress body has one node through the thickness (extent[1] = dx)");
     m->d = *d;
     m->nx = (int)n[0];
     m->ny = (int)n[1];
@@ -189,21 +196,30 @@ int material_from_params(const pd_mesh_s *m, const pd_params *p, Material *out)
     if (!(p->damping >= 0) || !(p->dt > 0) || p->n_steps < 0) return fail(PD_EINVAL, "bad damping, dt or n_steps");
     if (!std::isfinite(p->du)) return fail(PD_EINVAL, "du must be finite");
     double dx = m->d.dx;
+    const double t = m->d.thickness;
     out->delta = m->d.m_ratio * dx;
-    out->c_ref = 12.0 * p->E / (M_PI * std::pow(out->delta, 4));   // 3D micromodulus
-    out->volume = dx * dx * dx;
-    double d5 = std::pow(out->delta, 5);
-    // The appendix-A fracture energy of a 3D body is G_F = (pi delta^5 / 5) * A
-    // with A the area under the bond force-stretch curve between s0 and sc.
+    // bond stiffness constant (appendix A, Eq. bond_stiffness_constant)
+    if (t > 0) {
+        out->c_ref = 9.0 * p->E / (M_PI * t * std::pow(out->delta, 3));   // plane stress
+        out->volume = dx * dx * t;
+    } else {
+        out->c_ref = 12.0 * p->E / (M_PI * std::pow(out->delta, 4));      // 3D
+        out->volume = dx * dx * dx;
+    }
+    // The appendix-A fracture energy is G_F = (pi delta^5 / 5) A for a 3D
+    // body and (t delta^4 / 2) A in plane stress (the 2D integral of
+    // Eq. exp_fracture_energy_2D), with A the area under the bond
+    // force-stretch curve between s0 and sc.
     // EXPLIN: A = c s0 (sc - s0) I / (1 + alpha) with I = int_0^1 of the
     // normalised shape = 1/k - 1/(e^k - 1) + alpha / 2.
     // TRILINEAR: A = 0.2 c s0 (sc - s0).
     // Either way sc = s0 + gamma / (c s0).
+    const double geo = t > 0 ? 0.5 * t * std::pow(out->delta, 4) : M_PI * std::pow(out->delta, 5) / 5.0;
     if (p->law == PD_LAW_EXPLIN) {
         double I = 1.0 / p->k - 1.0 / std::expm1(p->k) + 0.5 * p->alpha;
-        out->gamma = 5.0 * p->GF * (1.0 + p->alpha) / (M_PI * d5 * I);
+        out->gamma = p->GF * (1.0 + p->alpha) / (geo * I);
     } else {
-        out->gamma = 25.0 * p->GF / (M_PI * d5);
+        out->gamma = p->GF / (geo * 0.2);
     }
     out->k = p->k;
     out->alpha = p->alpha;

@@ -21,17 +21,20 @@ constexpr int kModeChunk = 16;
 
 static unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// node-centre positions of a mesh, [M][3]
+// node-centre positions of a mesh, [M][3]; a plane-stress body's nodes lie
+// on the plane y = 0 whatever the spacing, so every level samples the field
+// on the same plane
 static std::vector<double> node_positions(const pd_mesh_s *m)
 {
     std::vector<double> X(3 * (size_t)m->M);
     const double dx = m->d.dx;
+    const bool plane = m->d.thickness > 0;
     for (int k = 0; k < m->nz; ++k)
         for (int j = 0; j < m->ny; ++j)
             for (int i = 0; i < m->nx; ++i) {
                 const int64_t n = i + (int64_t)m->nx * (j + (int64_t)m->ny * k);
                 X[3 * n] = (i + 0.5) * dx;
-                X[3 * n + 1] = (j + 0.5) * dx;
+                X[3 * n + 1] = plane ? 0.0 : (j + 0.5) * dx;
                 X[3 * n + 2] = (k + 0.5) * dx;
             }
     return X;
@@ -222,7 +225,9 @@ int pd_kl_build_exp(pd_mesh m, double corr_len, int32_t n_modes, pd_kl *out)
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(PD_EDEVICE, "no HIP device: the solver needs an MI355X (gfx950)");
     const int64_t n = m->M;
-    const double w = m->d.dx * m->d.dx * m->d.dx;
+    // midpoint weight: a cell's volume, or its area for a plane-stress body,
+    // whose random field lives on the plane
+    const double w = m->d.thickness > 0 ? m->d.dx * m->d.dx : m->d.dx * m->d.dx * m->d.dx;
     const std::vector<double> X = node_positions(m);
     DevMem mem;
     double *dX = nullptr, *dA = nullptr, *dD = nullptr, *dE = nullptr;
@@ -298,6 +303,8 @@ int pd_kl_extend(pd_kl kl, pd_mesh target, pd_kl *out)
 {
     if (!kl || !target || !out) return fail(PD_EINVAL, "null argument");
     if (kl->covariance != PD_COV_EXP || !kl->d_ext) return fail(PD_EINVAL, "only exponential bases can be extended");
+    if ((kl->mesh->d.thickness > 0) != (target->d.thickness > 0))
+        return fail(PD_EINVAL, "a plane-stress basis extends to plane-stress meshes only, a 3D one to 3D meshes");
     pd_kl_s *k = nullptr;
     int rc = extend_basis(kl, target, &k);
     if (rc) return rc;
@@ -341,7 +348,9 @@ int pd_fib_fields(pd_mesh m, const double *g_dev, int64_t n_samples, const pd_fi
     f.alpha_E = fp->alpha_E;
     f.delta_f = fp->delta_f;
     f.fck_min = fp->fck_min;
-    f.c_scale = 12.0 / (M_PI * delta * delta * delta * delta);
+    // micromodulus per unit E: the 3D or the plane-stress form of the mesh
+    const double t = m->d.thickness;
+    f.c_scale = t > 0 ? 9.0 / (M_PI * t * delta * delta * delta) : 12.0 / (M_PI * delta * delta * delta * delta);
     hipStream_t st = (hipStream_t)stream;
     if (out_dtype == PD_DTYPE_F64)
         fib_kernel<double><<<nblocks(n), 256, 0, st>>>(g_dev, n, f, (double *)s0_out, (double *)c_out, (double *)gf_out);

@@ -143,8 +143,8 @@ namespace pdmi {
 // geometry.cpp
 int build_mesh(const pd_mesh_desc *d, pd_mesh_s *m);
 int build_cuts(pd_mesh_s *m);
-double stencil_inv_len_sum();   // sum over the 122 offsets of 1/|v|
-double stability_limit(double rho, double c, double dx);
+double stencil_inv_len_sum(bool in_plane);   // sum of 1/|v| over the 122 (in plane: 28) offsets
+double stability_limit(const pd_mesh_s *m, double rho, double c);
 
 // material constants of a run, derived once on the host in FP64
 struct Material {

@@ -331,7 +331,7 @@ static int check_params(const pd_mesh_s *m, const pd_params *p, Material *mat, d
     if (rc) return rc;
     if (p->precision != PD_FP32 && p->precision != PD_FP64) return fail(PD_EINVAL, "unknown precision");
     if (p->accumulate != PD_ACC_KAHAN && p->accumulate != PD_ACC_PLAIN) return fail(PD_EINVAL, "unknown accumulate");
-    double dtc = stability_limit(p->rho, mat->c_ref * c_max_rel, m->d.dx);
+    double dtc = stability_limit(m, p->rho, mat->c_ref * c_max_rel);
     if (p->dt > dtc)
         return fail(PD_EUNSTABLE, "dt %.6g s exceeds the explicit stability limit %.6g s", p->dt, dtc);
     return PD_OK;

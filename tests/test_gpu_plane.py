@@ -1,0 +1,193 @@
+"""GPU parity of the plane-stress body (appendix A: plane-stress
+micromodulus and the 2D critical stretch; section 6.2: Specimen 3 at the
+levels of Table discretisation, 350 ... 89,600 nodes) with the oracle:
+force evaluations with heterogeneous fields, cracking runs at levels 0-2 in
+FP64 and FP32, every launch shape on the one-node-thick body, and a run
+driven by the paper's material model on the plane."""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G
+from oracle import material as OMAT
+from oracle import solver as S
+
+pytestmark = pytest.mark.gpu
+EPS64 = 2.0 ** -53
+EPS32 = 2.0 ** -24
+LC = 20e-3
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2212_04415_amd import beam as B
+    return torch, B
+
+
+def fp32_rounded(u, dx):
+    return (u / dx).astype(np.float32).astype(np.float64) * dx
+
+
+def force_bound(prob, u, precision):
+    s = prob.stretch(u)
+    cb = 0.5 * (prob.c[prob.bond_i] + prob.c[prob.bond_j])
+    sig = np.zeros(prob.n_nodes)
+    kap = np.zeros(prob.n_nodes)
+    for a in (prob.bond_i, prob.bond_j):
+        np.add.at(sig, a, np.abs(cb * s) * prob.volume)
+        np.add.at(kap, a, cb * prob.volume)
+    return 64 * EPS64 * (sig + kap) if precision == "f64" else 64 * EPS32 * sig
+
+
+def plane_fields(M, seed, n=1):
+    rng = np.random.default_rng(seed)
+    return (W.S0_MEAN * np.exp(0.2 * rng.standard_normal((n, M))),
+            np.exp(0.1 * rng.standard_normal((n, M))))
+
+
+# ---------------------------------------------------------------- force
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_plane_force_eval_matches_oracle(env, precision):
+    """Level 1 (70 x 1 x 20 nodes): random s0 and c fields, a smooth field
+    large enough that some bonds pass their limit stretch."""
+    torch, B = env
+    lv = W.level2d(1)
+    mesh = B.Mesh.for_level(lv)
+    assert mesh.shape == (70, 1, 20)
+    prob = S.beam_problem(lv)
+    s0, c_rel = plane_fields(mesh.n_nodes, 11)
+    prob = S.beam_problem(lv, s0=s0[0], c=prob.c * c_rel[0])
+    mesh.set_field(0, s0[0])
+    mesh.set_field(1, prob.c)
+    u = W.smooth_displacement(mesh.shape, lv.dx, 5e-6, seed=12)
+    u[:, 1] = 0.0
+    if precision == "f32":
+        u = fp32_rounded(u, lv.dx)
+    L = B.force_eval(mesh, B.make_params(lv, precision=precision), u)[0]
+    ref = prob.force(u)
+    assert np.any(prob.stretch(u) > 0.5 * (s0[0][prob.bond_i] + s0[0][prob.bond_j]))
+    err = np.max(np.abs(L - ref), axis=1)
+    bound = force_bound(prob, u, precision)
+    print(f"max err / bound = {np.max(err / bound):.3e}")
+    assert np.all(err <= bound)
+    assert np.all(L[:, 1] == 0)
+
+
+def test_plane_force_eval_full_size_level4(env):
+    """Level 4 at full size (560 x 1 x 160 = 89,600 nodes), eight samples in
+    one FP32 call; samples 0 and 7 compared node by node."""
+    torch, B = env
+    lv = W.level2d(4)
+    mesh = B.Mesh.for_level(lv)
+    M = mesh.n_nodes
+    assert M == 89600
+    n = 8
+    s0, _ = plane_fields(M, 13, n)
+    u = np.empty((n, M, 3))
+    for k in range(n):
+        u[k] = W.smooth_displacement(mesh.shape, lv.dx, 1.5e-6, seed=30 + k)
+        u[k][:, 1] = 0.0
+    u = fp32_rounded(u, lv.dx)
+    mesh.set_field(0, s0)
+    L = B.force_eval(mesh, B.make_params(lv, precision="f32"), u)
+    mesh.set_field(0, None)
+    for k in (0, n - 1):
+        prob = S.beam_problem(lv, s0=s0[k])
+        ref = prob.force(u[k])
+        err = np.max(np.abs(L[k] - ref), axis=1)
+        assert np.all(err <= force_bound(prob, u[k], "f32")), k
+
+
+# ---------------------------------------------------------------- runs
+@pytest.fixture(scope="module")
+def plane_refs():
+    lvs = [W.level2d(ell) for ell in (0, 1, 2)]
+    with cf.ThreadPoolExecutor(max_workers=3) as ex:
+        refs = list(ex.map(lambda lv: S.beam_problem(lv).run(), lvs))
+    return list(zip(lvs, refs))
+
+
+@pytest.mark.parametrize("ell", [0, 1, 2])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_plane_cracking_run_matches_oracle(env, plane_refs, ell, precision):
+    """Specimen 3 cracks from the notch at levels 0-2 (350 / 1,400 / 5,600
+    nodes): peak load, its step and the elastic reaction history."""
+    torch, B = env
+    lv, ref = plane_refs[ell]
+    assert 0.2 * lv.n_steps < ref["nstar"] < 0.8 * lv.n_steps
+    mesh = B.Mesh.for_level(lv)
+    out = B.run(mesh, B.make_params(lv, precision=precision, record_history=True), want_state=True)
+    q = ref["nstar"] // 3
+    if precision == "f64":
+        assert out["Q"] == pytest.approx(ref["Q"], rel=1e-9)
+        assert out["nstar"] == ref["nstar"]
+        assert np.linalg.norm(out["R"][:q] - ref["R"][:q]) < 1e-9 * np.linalg.norm(ref["R"][:q])
+    else:
+        assert out["Q"] == pytest.approx(ref["Q"], rel=5e-3)
+        assert abs(out["nstar"] - ref["nstar"]) <= 0.02 * lv.n_steps
+        assert np.linalg.norm(out["R"][:q] - ref["R"][:q]) < 2e-5 * np.linalg.norm(ref["R"][:q])
+    assert np.all(out["u"][:, 1] == 0)
+
+
+def test_plane_launch_shapes_agree_bitwise(env):
+    """Every launch shape gives the same peak, step and final state on the
+    one-node-thick body (the brick shapes run mostly ghost rows here)."""
+    torch, B = env
+    from paper_2212_04415_amd import pd
+    lv = W.level2d(1, steps_scale=0.5)
+    mesh = B.Mesh.for_level(lv)
+    s0, _ = plane_fields(mesh.n_nodes, 17)
+    mesh.set_field(0, s0[0])
+    outs = []
+    for shape in range(pd.PD_N_SHAPES):
+        mesh.set_launch_shape(shape)
+        outs.append(B.run(mesh, B.make_params(lv), want_state=True))
+    for o in outs[1:]:
+        assert o["Q"] == outs[0]["Q"] and o["nstar"] == outs[0]["nstar"]
+        assert np.array_equal(o["u"], outs[0]["u"]) and np.array_equal(o["kappa"], outs[0]["kappa"])
+    ref = S.beam_problem(lv, s0=s0[0]).run(want_state=False)
+    assert outs[0]["Q"] == pytest.approx(ref["Q"], rel=5e-3)
+
+
+# ---------------------------------------------------------------- material model
+def test_plane_paper_material_run_matches_oracle(env):
+    """The exponential-covariance field on the plane (Nystrom on the level-0
+    nodes, weight dx^2), extended to level 1, Weibull / fib fields with the
+    plane-stress micromodulus, and a batched FP32 cracking run at level 1."""
+    torch, B = env
+    lv0, lv1 = W.level2d(0), W.level2d(1)
+    m0, m1 = B.Mesh.for_level(lv0), B.Mesh.for_level(lv1)
+    X0 = G.node_positions(lv0.shape, lv0.dx)
+    X0[:, 1] = 0.0
+    ob = OMAT.ExpBasis(X0, lv0.dx ** 2, LC, 40)
+    kl0 = B.KL.exponential(m0, LC, 40)
+    assert kl0.n_modes == ob.n_modes
+    lam = kl0.eigenvalues()
+    assert np.allclose(lam, ob.lam, rtol=1e-10, atol=0)
+    kl1 = kl0.extend(m1)
+    n = 4
+    xi = W.kl_coefficients(21, n, ob.n_modes)
+    g = kl1.gaussian(torch.tensor(xi)).cpu().numpy()
+    X1 = G.node_positions(lv1.shape, lv1.dx)
+    X1[:, 1] = 0.0
+    gref = ob.gaussian(ob.evaluate(X1), xi)
+    assert np.max(np.abs(g - gref)) < 1e-8 * np.max(np.abs(gref))
+    delta = W.M_RATIO * lv1.dx
+    s0, c, gf = OMAT.material_fields(gref, delta, thickness=lv1.beam.thickness)
+    gs0, gc, ggf = (t.cpu().numpy() for t in B.fib_fields(m1, torch.tensor(gref)))
+    for a, b in ((gs0, s0), (gc, c), (ggf, gf)):
+        assert np.allclose(a, b, rtol=1e-13, atol=0)
+    dev = lambda a: torch.tensor(a, device="cuda", dtype=torch.float32).contiguous()
+    Q, ns, st = B.run_batch([B.BatchItem(m1, B.make_params(lv1), n, dev(s0), dev(c), dev(gf))])[0]
+    assert torch.all(st == 0)
+    with cf.ThreadPoolExecutor(max_workers=n) as ex:
+        refs = list(ex.map(lambda k: S.beam_problem(lv1, s0=s0[k], c=c[k], gf=gf[k]).run(want_state=False),
+                           range(n)))
+    for k, ref in enumerate(refs):
+        assert ref["nstar"] < lv1.n_steps
+        assert Q[k].item() == pytest.approx(ref["Q"], rel=5e-3)

@@ -29,9 +29,10 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(pd.SIGNATURES)
 
 
-def build(beam, dx, m_ratio=W.M_RATIO):
-    desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, beam.thickness, beam.depth), dx, m_ratio,
-                           beam.span, beam.notch_depth, beam.pad_width)
+def build(beam, dx, m_ratio=W.M_RATIO, extent_y=None, thickness=0.0):
+    desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, beam.thickness if extent_y is None else extent_y,
+                                            beam.depth), dx, m_ratio, beam.span, beam.notch_depth, beam.pad_width,
+                           thickness)
     h = C.c_void_p()
     rc = pd.lib().pd_build_mesh(C.byref(desc), C.byref(h))
     return rc, h
@@ -114,3 +115,36 @@ def test_launch_shape_pinning_is_validated():
         assert pd.lib().pd_autotune(None, None, 1, None, None, None) == pd.PD_EINVAL
     finally:
         pd.lib().pd_free_mesh(h)
+
+
+@pytest.mark.parametrize("ell", [0, 2, 4])
+def test_host_geometry_plane_specimen_matches_oracle(ell):
+    """The plane-stress Specimen 3 (one node thick) at the paper's levels."""
+    lv = W.level2d(ell)
+    rc, h = build(lv.beam, lv.dx, extent_y=lv.dx, thickness=lv.beam.thickness)
+    assert rc == 0, pd.pd_last_error()
+    try:
+        nb = C.c_int64()
+        assert pd.lib().pd_build_bonds(h, C.byref(nb)) == 0, pd.pd_last_error()
+        info = pd.pd_mesh_info_t()
+        pd.pd_mesh_get_info(h, C.byref(info))
+        shape = lv.shape
+        assert (info.nx, info.ny, info.nz) == shape and shape[1] == 1
+        bi, bj, _ = G.unique_bonds(shape, W.M_RATIO)
+        cut = G.notch_cut_mask(shape, lv.dx, bi, bj, 0.5 * lv.beam.length, lv.beam.notch_depth)
+        assert nb.value == info.n_bonds == bi.size - cut.sum()
+        sup = np.zeros(info.n_support, dtype=np.int32)
+        ld = np.zeros(info.n_load, dtype=np.int32)
+        pd.pd_mesh_get_pads(h, sup.ctypes.data, ld.ctypes.data)
+        osup, old = G.beam_pads(shape, lv.dx, lv.beam)
+        assert np.array_equal(np.sort(sup), osup) and np.array_equal(np.sort(ld), old)
+    finally:
+        pd.pd_free_mesh(h)
+
+
+@pytest.mark.parametrize("extent_y,thickness", [(2 * 10e-3, 50e-3), (10e-3, -1.0)])
+def test_plane_mesh_rejects_bad_thickness(extent_y, thickness):
+    """A plane body must be one node thick and its thickness non-negative."""
+    rc, h = build(W.SPECIMEN3, 10e-3, extent_y=extent_y, thickness=thickness)
+    assert rc == pd.PD_EINVAL and not h.value
+    assert "thick" in pd.pd_last_error()

@@ -72,6 +72,7 @@ class Beam:
     span: float = 150.0 * MM
     notch_depth: float = 5.0 * MM
     pad_width: float = 5.0 * MM
+    plane: bool = False             # plane stress: one node through the thickness
 
     @staticmethod
     def similar(depth: float) -> "Beam":
@@ -94,8 +95,8 @@ class Level:
 
     @property
     def shape(self):
-        return tuple(int(round(L / self.dx)) for L in
-                     (self.beam.length, self.beam.thickness, self.beam.depth))
+        t = self.dx if self.beam.plane else self.beam.thickness
+        return tuple(int(round(L / self.dx)) for L in (self.beam.length, t, self.beam.depth))
 
 
 def level(ell: int, fracture: bool = False, beam: Beam = Beam(),
@@ -117,6 +118,25 @@ class Config:
     seed: int
     precision: str            # "f32" or "f64"
     random_field: bool
+
+
+# ---------------------------------------------------------------- plane stress
+# Specimen 3 of section 6.2 as the paper models it: a 2D plane-stress body,
+# 350 x 100 mm, 50 mm thick, span 250 mm, half-notched; levels dx = 10 / 5 /
+# 2.5 / 1.25 / 0.625 mm (Table discretisation: 350 ... 89,600 nodes).
+SPECIMEN3 = Beam(length=350.0 * MM, thickness=50.0 * MM, depth=100.0 * MM, span=250.0 * MM,
+                 notch_depth=50.0 * MM, pad_width=12.0 * MM, plane=True)
+DT_2D_L0 = 2.0e-6           # s at dx = 10 mm (0.67 of the 2D stability limit)
+STEPS_2D_L0 = 2000
+DU_2D_L0 = 5.0e-8           # m per step at dx = 10 mm (peak load mid-run)
+
+
+def level2d(ell: int, law: int = LAW_TRILINEAR, steps_scale: float = 1.0) -> Level:
+    """Level ell of the plane-stress Specimen 3: dx = 10 mm / 2^ell with dt,
+    steps and the displacement increment scaled with dx."""
+    r = 2 ** ell
+    return Level(beam=SPECIMEN3, dx=10.0 * MM / r, dt=DT_2D_L0 / r,
+                 n_steps=int(round(STEPS_2D_L0 * r * steps_scale)), du=DU_2D_L0 / r, law=law)
 
 
 def configs(fracture: bool = False) -> List[Config]:
