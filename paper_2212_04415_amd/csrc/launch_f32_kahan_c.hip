@@ -4,9 +4,9 @@
 
 namespace pdmi {
 
-void launch_f32_kahan_c(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a)
+void launch_f32_kahan_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a)
 {
-    launch_shape<float, true, true>(shape, grid, st, a);
+    launch_shape<float, true, true>(shape, plane, grid, st, a);
 }
 
 }  // namespace pdmi

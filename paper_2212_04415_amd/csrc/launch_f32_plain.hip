@@ -4,14 +4,14 @@
 
 namespace pdmi {
 
-void launch_f32_plain(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a)
+void launch_f32_plain(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a)
 {
-    launch_shape<float, false, false>(shape, grid, st, a);
+    launch_shape<float, false, false>(shape, plane, grid, st, a);
 }
 
-void launch_f32_plain_c(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a)
+void launch_f32_plain_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a)
 {
-    launch_shape<float, false, true>(shape, grid, st, a);
+    launch_shape<float, false, true>(shape, plane, grid, st, a);
 }
 
 }  // namespace pdmi

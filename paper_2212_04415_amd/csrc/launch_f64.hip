@@ -4,14 +4,14 @@
 
 namespace pdmi {
 
-void launch_f64(int shape, dim3 grid, hipStream_t st, const StepParams<double> &a)
+void launch_f64(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<double> &a)
 {
-    launch_shape<double, false, false>(shape, grid, st, a);
+    launch_shape<double, false, false>(shape, plane, grid, st, a);
 }
 
-void launch_f64_c(int shape, dim3 grid, hipStream_t st, const StepParams<double> &a)
+void launch_f64_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<double> &a)
 {
-    launch_shape<double, false, true>(shape, grid, st, a);
+    launch_shape<double, false, true>(shape, plane, grid, st, a);
 }
 
 }  // namespace pdmi

@@ -184,6 +184,17 @@ constexpr LaunchShape kShapes[PD_N_SHAPES] = {
     {8, 4, 4, 128, true},    // PD_SHAPE_LDS_8x4x4
     {256, 1, 1, 256, false}, // PD_SHAPE_GLOBAL_256
 };
+// the same shape indices on a body one node thick: planar patches
+constexpr LaunchShape kPlaneShapes[PD_N_SHAPES] = {
+    {64, 1, 4, 256, true},
+    {32, 1, 8, 256, true},
+    {32, 1, 4, 128, true},
+    {256, 1, 1, 256, false},
+};
+
+// A body one node thick has neighbours in the x-z plane only; its step
+// kernels visit the 28 in-plane offsets.
+static inline bool plane_mesh(const pd_mesh_s *m) { return m->ny == 1; }
 
 // Common state of one (mesh, params, samples) solve.
 struct Solve {
@@ -240,7 +251,7 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     a.P = m->P;
     a.M = m->M;
     a.PXY = (int64_t)m->PX * m->PY;
-    const LaunchShape &sh = kShapes[effective_shape(b.f64, b.kahan, b.has_c, s.shape)];
+    const LaunchShape &sh = (plane_mesh(m) ? kPlaneShapes : kShapes)[effective_shape(b.f64, b.kahan, b.has_c, s.shape)];
     a.nbx = (m->nx + sh.bx - 1) / sh.bx;
     a.nby = (m->ny + sh.by - 1) / sh.by;
     const int64_t nbz = (m->nz + sh.bz - 1) / sh.bz;

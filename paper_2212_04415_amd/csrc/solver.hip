@@ -28,17 +28,18 @@ static void launch_step_impl(const Solve &s, int k_local, hipStream_t st, double
     }
     dim3 grid((unsigned)((a.n_items + kXcds - 1) / kXcds * kXcds));
     const int shape = effective_shape(s.b.f64, s.b.kahan, s.b.has_c, s.shape);
+    const bool plane = plane_mesh(s.m);
     if constexpr (sizeof(T) == 4) {
         if (s.b.kahan) {
-            if (s.b.has_c) launch_f32_kahan_c(shape, grid, st, a);
-            else launch_f32_kahan(shape, grid, st, a);
+            if (s.b.has_c) launch_f32_kahan_c(shape, plane, grid, st, a);
+            else launch_f32_kahan(shape, plane, grid, st, a);
         } else {
-            if (s.b.has_c) launch_f32_plain_c(shape, grid, st, a);
-            else launch_f32_plain(shape, grid, st, a);
+            if (s.b.has_c) launch_f32_plain_c(shape, plane, grid, st, a);
+            else launch_f32_plain(shape, plane, grid, st, a);
         }
     } else {
-        if (s.b.has_c) launch_f64_c(shape, grid, st, a);
-        else launch_f64(shape, grid, st, a);
+        if (s.b.has_c) launch_f64_c(shape, plane, grid, st, a);
+        else launch_f64(shape, plane, grid, st, a);
     }
 }
 

@@ -1,7 +1,8 @@
 // Device code of one explicit time step of the bond-based peridynamic solve.
 //
 // A step evaluates, for every node of every sample, the bond forces over its
-// 122-point horizon (paper section 2.1, Eq. PD_Force_Function and
+// 122-point horizon (28 in-plane points on a body one node thick, the
+// plane-stress model of appendix A) (paper section 2.1, Eq. PD_Force_Function and
 // Eq. PD_EOM_Dynamic; appendix A, Eq. exp_scalar_force and
 // Eq. exp_damage_parameter), sums them with compensated accumulation, closes
 // the damped velocity-Verlet step and opens the next one.  The first block of
@@ -46,11 +47,27 @@ constexpr int kXcds = 8;
 // those two rows on disjoint banks.
 template <int BX_, int BY_, int BZ_, int PADX = 0>
 struct Brick {
+    static constexpr bool PLANE = false;
     static constexpr int BX = BX_, BY = BY_, BZ = BZ_;
     static constexpr int N = BX * BY * BZ;
     static constexpr int LX = BX + 2 * kHalo + PADX, LY = BY + 2 * kHalo, LZ = BZ + 2 * kHalo;
     static constexpr int LXY = LX * LY;
     static constexpr int TILE = LX * LY * LZ;
+    static_assert(N % 64 == 0, "a brick is whole wavefronts");
+};
+
+// The same for a body one node thick (every node at y = 0; its neighbours
+// all lie in the x-z plane): a BX x BZ patch whose tile has no y halo, and
+// the fast loop visits the 14 in-plane offset pairs only.  Rows of 32 or
+// more cells fill whole 128-bit LDS phases, so no row padding is needed.
+template <int BX_, int BZ_>
+struct PlaneBrick {
+    static constexpr bool PLANE = true;
+    static constexpr int BX = BX_, BY = 1, BZ = BZ_;
+    static constexpr int N = BX * BZ;
+    static constexpr int LX = BX + 2 * kHalo, LY = 1, LZ = BZ + 2 * kHalo;
+    static constexpr int LXY = LX;
+    static constexpr int TILE = LX * LZ;
     static_assert(N % 64 == 0, "a brick is whole wavefronts");
 };
 
@@ -282,34 +299,45 @@ __device__ __forceinline__ void pipe_step(R (&ring)[D], LoadF &load, CompF &comp
     }
 }
 
-template <int D, typename R, typename LoadF, typename CompF, int... I>
+template <int N, int D, typename R, typename LoadF, typename CompF, int... I>
 __device__ __forceinline__ void pipeline(LoadF &load, CompF &comp, std::integer_sequence<int, I...>)
 {
     R ring[D];
     ((ring[I] = load(std::integral_constant<int, I>{})), ...);
-    pipe_step<0, kHalfStencil, D>(ring, load, comp);
+    pipe_step<0, N, D>(ring, load, comp);
 }
 
-// Order in which the fast loop visits the 61 offset pairs: by |v|^2, then by
-// slot, so that bonds of one length are contiguous (their series
-// coefficients and scaled thresholds are shared).
+// Order in which the fast loop visits the 61 offset pairs (the 14 with
+// v_y = 0 on a plane body): by |v|^2, then by slot, so that bonds of one
+// length are contiguous (their series coefficients and scaled thresholds are
+// shared).  Slots keep their 3D numbering either way.
 struct PairOrder {
     int k[kHalfStencil];
+    int n;
 };
 
 constexpr int half_len2(int k) { return kHalf.v[k].x * kHalf.v[k].x + kHalf.v[k].y * kHalf.v[k].y + kHalf.v[k].z * kHalf.v[k].z; }
 
-constexpr PairOrder make_pair_order()
+constexpr PairOrder make_pair_order(bool plane)
 {
     PairOrder o{};
-    int n = 0;
+    o.n = 0;
     for (int l = 1; l <= 9; ++l)
         for (int k = 0; k < kHalfStencil; ++k)
-            if (half_len2(k) == l) o.k[n++] = k;
+            if (half_len2(k) == l && (!plane || kHalf.v[k].y == 0)) o.k[o.n++] = k;
     return o;
 }
 
-constexpr PairOrder kPairOrder = make_pair_order();
+constexpr PairOrder kPairOrder = make_pair_order(false);
+constexpr PairOrder kPairOrderPlane = make_pair_order(true);
+static_assert(kPairOrder.n == kHalfStencil && kPairOrderPlane.n == 14, "stencil pair counts");
+
+template <bool PLANE> struct Pairs {
+    static constexpr const PairOrder &order = kPairOrder;
+};
+template <> struct Pairs<true> {
+    static constexpr const PairOrder &order = kPairOrderPlane;
+};
 
 template <typename T> struct FastLoad {
     typename Vec4<T>::t a, b;
@@ -343,14 +371,16 @@ template <typename T> struct FastLoad {
 // rounding (2^-24 = 6e-8).  FP64 and the exception pass use the closed form.
 constexpr double kSeriesBound = 1.0 / 1024;
 
-template <typename T, bool KAHAN, bool HAS_C, bool MASKED, typename Src>
+template <typename T, bool KAHAN, bool HAS_C, bool MASKED, bool PLANE, typename Src>
 __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src,
                                           const typename Vec4<T>::t &ui, T ci, T thr,
                                           Acc3<T, KAHAN> &acc, bool &flag, const uint32_t (&skip)[4],
                                           uint32_t (&exc)[4])
 {
+    using PO = Pairs<PLANE>;
+    constexpr int NP = PO::order.n;
     auto load = [&](auto ic) {
-        constexpr Off v = kHalf.v[kPairOrder.k[decltype(ic)::value]];
+        constexpr Off v = kHalf.v[PO::order.k[decltype(ic)::value]];
         FastLoad<T> r;
         r.a = src.template get<v.x, v.y, v.z>();
         r.b = src.template get<-v.x, -v.y, -v.z>();
@@ -369,7 +399,7 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
     T pend_x = T(0), pend_y = T(0), pend_z = T(0);   // partial sum of the current group of pairs
     auto comp_pair = [&](auto ic, const FastLoad<T> &r) {
         constexpr int I = decltype(ic)::value;
-        constexpr int K = kPairOrder.k[I];
+        constexpr int K = PO::order.k[I];
         constexpr Off v = kHalf.v[K];
         constexpr int V2 = v.x * v.x + v.y * v.y + v.z * v.z;
         T eax, eay, eaz, ebx, eby, ebz, wa, wb;
@@ -391,8 +421,8 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
                 exa = (nwa > ts) || (nwa < T(-kSeriesBound) * S2);
                 exb = (nwb > ts) || (nwb < T(-kSeriesBound) * S2);
             } else {
-                constexpr bool gfirst = I == 0 || half_len2(kPairOrder.k[I > 0 ? I - 1 : 0]) != V2;
-                constexpr bool glast = I + 1 == kHalfStencil || half_len2(kPairOrder.k[I + 1 < kHalfStencil ? I + 1 : I]) != V2;
+                constexpr bool gfirst = I == 0 || half_len2(PO::order.k[I > 0 ? I - 1 : 0]) != V2;
+                constexpr bool glast = I + 1 == NP || half_len2(PO::order.k[I + 1 < NP ? I + 1 : I]) != V2;
                 if constexpr (gfirst) {
                     hi = fmax(nwa, nwb);
                     ha = fmax(fabs(nwa), fabs(nwb));
@@ -446,11 +476,11 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         pend_x = part(std::integral_constant<int, v.x>{}, eax, ebx, pend_x);
         pend_y = part(std::integral_constant<int, v.y>{}, eay, eby, pend_y);
         pend_z = part(std::integral_constant<int, v.z>{}, eaz, ebz, pend_z);
-        if constexpr (I % G == G - 1 || I + 1 == kHalfStencil) acc.add(pend_x, pend_y, pend_z);
+        if constexpr (I % G == G - 1 || I + 1 == NP) acc.add(pend_x, pend_y, pend_z);
     };
     // neighbours read through the caches hold more registers in flight
     constexpr int D = (sizeof(T) == 4 && Src::kLds) ? PD_PIPE_DEPTH : 2;
-    pipeline<D, FastLoad<T>>(load, comp_pair, std::make_integer_sequence<int, D>{});
+    pipeline<NP, D, FastLoad<T>>(load, comp_pair, std::make_integer_sequence<int, D>{});
     if constexpr (MASKED) flag = false;
     // thr <= 2^-10, so this flags exactly the bonds the masked form excepts
     else if constexpr (sizeof(T) == 4) flag = fl;
@@ -625,7 +655,7 @@ __device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int samp
 }
 
 // Forces and Verlet update of one node, given its neighbour source.
-template <typename T, bool KAHAN, bool HAS_C, typename Src>
+template <typename T, bool KAHAN, bool HAS_C, bool PLANE, typename Src>
 __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab, int sample,
                                           int64_t n, int64_t node, int64_t p, const typename Vec4<T>::t &ui)
 {
@@ -656,7 +686,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
             const uint32_t none[4] = {0u, 0u, 0u, 0u};
             uint32_t unused[4] = {0u, 0u, 0u, 0u};
             bool flag = false;
-            fast_loop<T, KAHAN, HAS_C, false>(a, src, ui, ci, thr, acc, flag, none, unused);
+            fast_loop<T, KAHAN, HAS_C, false, PLANE>(a, src, ui, ci, thr, acc, flag, none, unused);
             if (flag) {
                 acc.zero();
                 masked = true;
@@ -670,7 +700,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         const uint32_t skip[4] = {cm.x | d0.x, cm.y | d0.y, cm.z | d0.z, cm.w | d0.w};
         uint32_t exc[4] = {0u, 0u, 0u, 0u};
         bool unused = false;
-        fast_loop<T, KAHAN, HAS_C, true>(a, src, ui, ci, thr, acc, unused, skip, exc);
+        fast_loop<T, KAHAN, HAS_C, true, PLANE>(a, src, ui, ci, thr, acc, unused, skip, exc);
         const uint32_t todo[4] = {exc[0] & ~cm.x, exc[1] & ~cm.y, exc[2] & ~cm.z, exc[3] & ~cm.w};
         uint32_t dm[4] = {d0.x, d0.y, d0.z, d0.w};
         T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
@@ -755,12 +785,14 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
     fill_slot_lds(tab);
     if constexpr (LDS) {
         const int bx = (int)(t % a.nbx), by = (int)((t / a.nbx) % a.nby), bz = (int)(t / ((int64_t)a.nbx * a.nby));
-        // the tile's first padded cell is the brick origin (node + kHalo - kHalo)
+        // the tile's first padded cell is the brick origin (node + kHalo - kHalo);
+        // a plane tile is the single row y = 0 (padded row kHalo)
         const int x0 = bx * BR::BX, y0 = by * BR::BY, z0 = bz * BR::BZ;
         constexpr int WX = BR::BX + 2 * kHalo;   // cells per row that hold data
+        constexpr int YH = BR::PLANE ? 0 : kHalo; // y halo of the tile
         for (int q = threadIdx.x; q < WX * BR::LY * BR::LZ; q += BR::N) {
             const int lx = q % WX, ly = (q / WX) % BR::LY, lz = q / (WX * BR::LY);
-            const int px = x0 + lx, py = y0 + ly, pz = z0 + lz;
+            const int px = x0 + lx, py = y0 + ly + (kHalo - YH), pz = z0 + lz;
             const bool in = px < a.PX && py < a.PY && pz < a.PZ;
             const int64_t gi = px + (int64_t)py * a.PX + (int64_t)pz * a.PXY;
             V4 v{};
@@ -774,9 +806,9 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         if (ix >= a.nx || iy >= a.ny || iz >= a.nz) return;
         const int64_t node = ix + (int64_t)a.nx * (iy + (int64_t)a.ny * iz);
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
-        const int c = (tx + kHalo) + BR::LX * (ty + kHalo) + BR::LXY * (tz + kHalo);
+        const int c = (tx + kHalo) + BR::LX * (ty + YH) + BR::LXY * (tz + kHalo);
         const LdsSrc<T, BR> src{tile, ctile, c};
-        node_step<T, KAHAN, HAS_C>(a, src, tab, sample, n, node, p, tile[c]);
+        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, tile[c]);
     } else {
         __syncthreads();
         const int64_t node = t * BR::N + threadIdx.x;
@@ -789,7 +821,7 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
         const GlobalSrc<T> src{U, (uint32_t)p * (uint32_t)sizeof(V4), a.PX, a.PXY,
                                HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr, (uint32_t)p * (uint32_t)sizeof(T)};
-        node_step<T, KAHAN, HAS_C>(a, src, tab, sample, n, node, p, U[p]);
+        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, U[p]);
     }
 }
 

@@ -13,8 +13,25 @@ namespace pdmi {
 
 #ifdef PD_STEP_LAUNCH_IMPL
 template <typename T, bool KAHAN, bool HAS_C>
-static void launch_shape(int shape, dim3 grid, hipStream_t st, const StepParams<T> &a)
+static void launch_shape(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<T> &a)
 {
+    if (plane) {
+        if constexpr (sizeof(T) == 4 && KAHAN && !HAS_C) {
+            switch (shape) {
+            case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<64, 4>><<<grid, 256, 0, st>>>(a); return;
+            case PD_SHAPE_LDS_8x8x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<32, 8>><<<grid, 256, 0, st>>>(a); return;
+            case PD_SHAPE_LDS_8x4x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<32, 4>><<<grid, 128, 0, st>>>(a); return;
+            default: break;
+            }
+        } else if constexpr (sizeof(T) == 4) {
+            if (shape == PD_SHAPE_LDS_16x4x4) {
+                step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<64, 4>><<<grid, 256, 0, st>>>(a);
+                return;
+            }
+        }
+        step_kernel<T, KAHAN, HAS_C, false, PlaneBrick<256, 1>><<<grid, 256, 0, st>>>(a);
+        return;
+    }
     if constexpr (sizeof(T) == 4 && KAHAN && !HAS_C) {
         switch (shape) {
         case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4, 2>><<<grid, 256, 0, st>>>(a); return;
@@ -32,11 +49,12 @@ static void launch_shape(int shape, dim3 grid, hipStream_t st, const StepParams<
 }
 #endif
 
-void launch_f32_kahan(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
-void launch_f32_kahan_c(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
-void launch_f32_plain(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
-void launch_f32_plain_c(int shape, dim3 grid, hipStream_t st, const StepParams<float> &a);
-void launch_f64(int shape, dim3 grid, hipStream_t st, const StepParams<double> &a);
-void launch_f64_c(int shape, dim3 grid, hipStream_t st, const StepParams<double> &a);
+// plane: the mesh is one node thick (PlaneBrick instantiations)
+void launch_f32_kahan(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f32_kahan_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f32_plain(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f32_plain_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a);
+void launch_f64(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<double> &a);
+void launch_f64_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<double> &a);
 
 }  // namespace pdmi
