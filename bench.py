@@ -177,6 +177,35 @@ def sweep_leg(steps=1000):
     return out
 
 
+def plane_leg(samples=(2048, 512, 128, 32, 8)):
+    """The paper's own case: the plane-stress Specimen 3 (350 x 100 mm,
+    t = 50 mm, half-notched) on the five levels of its Table discretisation
+    (350 ... 89,600 nodes), the paper's material model (exponential
+    covariance on the plane, Weibull strength, fib relations), every level-l
+    sample paired with a coarse solve on the same coefficients, one batched
+    FP32 call."""
+    import torch
+    import workloads as W
+    from paper_2212_04415_amd import mlmc
+    levels = [W.level2d(l) for l in range(len(samples))]
+    out = mlmc.coupled_batch(levels, list(samples), seed=5, precision="f32", corr_len=20e-3,
+                             n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
+                             kl_coefficients=W.kl_coefficients, field_model="paper")
+    bu = sum(b * n * st for b, n, st in zip(out["bonds"], out["solves"], out["steps"]))
+    L = len(samples)
+    fine = [torch.tensor(out["Q"][l][:samples[l]], device="cuda") for l in range(L)]
+    coarse = [None] + [torch.tensor(out["Q"][l - 1][samples[l - 1]:samples[l - 1] + samples[l]], device="cuda")
+                       for l in range(1, L)]
+    u = [0.05, 0.5, 0.95]
+    quant = mlmc.cdf(fine, coarse, u)
+    return {"workload": "specimen3_plane_stress_paper_material", "nodes": out["nodes"], "bonds": out["bonds"],
+            "steps": out["steps"], "solves_per_level": out["solves"], "wall_s": out["wall_s"],
+            "bond_updates_per_s": bu / out["wall_s"], "mlmc_samples_per_s": sum(samples) / out["wall_s"],
+            "estimate_N": out["estimate"], "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "level_mean_var": [[m, v] for m, v, _ in out["levels"]],
+            "multilevel_quantiles_N": {str(k): float(v) for k, v in zip(u, quant)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +222,8 @@ def main():
                     help="also run the adaptive MLMC algorithm on the three levels (RMSE target 80 N)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the size-sweep beams (D = 50..400 mm, 32 samples, first 1000 steps)")
+    ap.add_argument("--plane", action="store_true",
+                    help="also run the plane-stress Specimen-3 MLMC hierarchy (five levels, paper material model)")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="profiling only: time steps per batch solve (default: the workload's 8000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -323,6 +354,8 @@ def main():
         line["mlmc_adaptive"] = adaptive_leg()
     if args.sweep:
         line["size_sweep"] = sweep_leg()
+    if args.plane:
+        line["plane_stress_mlmc"] = plane_leg()
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
