@@ -401,6 +401,21 @@ static hipStream_t capture_stream()
     return s;
 }
 
+// n streams (default priority) for the branches of a captured multi-item
+// graph; the calling thread keeps them for later batches
+static int branch_streams(int n, std::vector<hipStream_t> &out)
+{
+    static thread_local std::vector<hipStream_t> pool;
+    while ((int)pool.size() < n) {
+        hipStream_t x = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        pool.push_back(x);
+    }
+    out.assign(pool.begin(), pool.begin() + n);
+    return PD_OK;
+}
+
 constexpr int kChunk = 64;  // steps per captured graph (even)
 
 // Enqueue all steps of a solve on st: whole chunks from a graph, then the

@@ -445,27 +445,47 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         // one hyper-period of 2 * lcm ticks: every item takes an even number
         // of steps in it, so the ping-pong parity of a replay is fixed
         int64_t H = 2 * lcm * std::max<int64_t>(1, 32 / lcm);
+        // The items share no mutable state, so each one's chain of steps is
+        // a branch of its own in the graph (forked from and joined into the
+        // capture stream): a small level's launches fill the CUs that a
+        // large level's tail leaves idle.  Every branch runs its steps in
+        // order, so the results do not depend on how the branches overlap.
         hipStream_t cap = capture_stream();
+        std::vector<hipStream_t> br;
+        std::vector<hipEvent_t> ev(n_items + 1, nullptr);
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        rc = branch_streams(n_items, br);
+        for (auto &x : ev) {
+            if (rc) break;
+            hipError_t ee = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+            if (ee != hipSuccess) rc = hip_fail(ee, "hipEventCreate");
+        }
+        hipError_t e = rc ? hipSuccess : hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) rc = hip_fail(e, "hipStreamBeginCapture");
         if (!rc) {
-            for (int64_t t = 0; t < H; ++t)
-                for (int i = 0; i < n_items; ++i) {
-                    if (t % ratio[i]) continue;
-                    int k_local = (int)(t / ratio[i]);
-                    if (f64) launch_step<double>(solves[i], k_local, cap);
-                    else launch_step<float>(solves[i], k_local, cap);
+            e = hipEventRecord(ev[n_items], cap);
+            for (int i = 0; e == hipSuccess && i < n_items; ++i) {
+                e = hipStreamWaitEvent(br[i], ev[n_items], 0);
+                if (e != hipSuccess) break;
+                for (int64_t k = 0; k < H / ratio[i]; ++k) {
+                    if (f64) launch_step<double>(solves[i], (int)k, br[i]);
+                    else launch_step<float>(solves[i], (int)k, br[i]);
                 }
-            for (int i = 0; i < n_items; ++i) launch_advance(solves[i], H / ratio[i], cap);
+                launch_advance(solves[i], H / ratio[i], br[i]);
+                e = hipEventRecord(ev[i], br[i]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(cap, ev[i], 0);
+            }
+            if (e != hipSuccess) rc = hip_fail(e, "graph branches");
             e = hipStreamEndCapture(cap, &g);
-            if (e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+            if (e != hipSuccess && !rc) rc = hip_fail(e, "hipStreamEndCapture");
         }
         if (!rc) {
             e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
             if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
         }
         if (g) (void)hipGraphDestroy(g);
+        for (auto x : ev)
+            if (x) (void)hipEventDestroy(x);
         for (int64_t done = 0; !rc && done < ticks; done += H) {
             e = hipGraphLaunch(exec, st);
             if (e != hipSuccess) rc = hip_fail(e, "hipGraphLaunch");
