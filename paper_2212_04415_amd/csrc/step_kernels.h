@@ -260,6 +260,15 @@ struct GlobalSrc {
     {
         return ld(Cp, (int64_t)x + (int64_t)y * PX + (int64_t)z * PXY, lbc);
     }
+    // the node's position key, and the source seen from another node's key
+    __device__ __forceinline__ uint32_t key() const { return lb; }
+    __device__ __forceinline__ GlobalSrc rebased(uint32_t k) const
+    {
+        GlobalSrc r = *this;
+        r.lb = k;
+        r.lbc = k / (uint32_t)(sizeof(V4) / sizeof(T));
+        return r;
+    }
 };
 
 // ... from the block's LDS tiles (brick plus halo)
@@ -280,6 +289,13 @@ struct LdsSrc {
         return ctile[c + X + BR::LX * Y + BR::LXY * Z];
     }
     __device__ __forceinline__ T getc(int x, int y, int z) const { return ctile[c + x + BR::LX * y + BR::LXY * z]; }
+    __device__ __forceinline__ uint32_t key() const { return (uint32_t)c; }
+    __device__ __forceinline__ LdsSrc rebased(uint32_t k) const
+    {
+        LdsSrc r = *this;
+        r.c = (int)k;
+        return r;
+    }
 };
 
 // ---------------------------------------------------------------- pipelining
@@ -550,59 +566,200 @@ __device__ __forceinline__ void fill_slot_lds(SlotLds<T> &t)
     if (threadIdx.x < 10) t.len[threadIdx.x] = (T)c_sqrt_int[threadIdx.x];
 }
 
-// The bonds the masked fast loop left out (todo = its exceptions minus the
-// notch-cut bonds), one at a time in slot order: closed-form stretch,
-// damage history and damage law.  A bond's largest stretch is kept in hist
-// once it passes the bond's limit stretch (never decreasing, so damage never
-// heals), and its bit in dm marks it damaged; a bond whose bit is clear has
-// never passed its limit and has d = 0.  Ghost neighbours contribute nothing.
-template <typename T, bool KAHAN, bool HAS_C, typename Src>
-__device__ __forceinline__ void exc_loop(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
-                                         const T *__restrict__ S0, T *__restrict__ Hs,
-                                         uint32_t lb1, int64_t node, const typename Vec4<T>::t &ui, T s0i, T ci,
-                                         const T *__restrict__ Gp, int gstep, T gi, const uint32_t (&todo)[4],
-                                         uint32_t (&dm)[4],
-                                         Acc3<T, KAHAN> &acc)
+// Cross-lane helpers of the pooled exception pass (wave64; every lane of the
+// wave takes part).
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);
+}
+__device__ __forceinline__ float shfl_t(float v, uint32_t src)
+{
+    return __builtin_bit_cast(float, shfl_u32(__builtin_bit_cast(uint32_t, v), src));
+}
+__device__ __forceinline__ double shfl_t(double v, uint32_t src)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = shfl_u32((uint32_t)b, src), hi = shfl_u32((uint32_t)(b >> 32), src);
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
+// Bit k of a 128-bit mask held in four registers (selects, not an indexed
+// array, so the mask stays in registers).
+__device__ __forceinline__ bool mask_bit(const uint32_t (&m)[4], int k)
+{
+    const int w = k >> 5;
+    const uint32_t v = w == 0 ? m[0] : w == 1 ? m[1] : w == 2 ? m[2] : m[3];
+    return (v >> (k & 31)) & 1u;
+}
+__device__ __forceinline__ void set_mask_bit(uint32_t (&m)[4], int k)
+{
+    const int w = k >> 5;
+    const uint32_t b = 1u << (k & 31);
+    m[0] |= w == 0 ? b : 0u;
+    m[1] |= w == 1 ? b : 0u;
+    m[2] |= w == 2 ? b : 0u;
+    m[3] |= w == 3 ? b : 0u;
+}
+
+// Takes the lowest set bit of the 128-bit mask m (word order 0..3) and
+// returns its slot, or -1 when m is empty.
+__device__ __forceinline__ int pop_slot(uint32_t (&m)[4])
+{
+    if (m[0]) {
+        const int b = __builtin_ctz(m[0]);
+        m[0] &= m[0] - 1u;
+        return b;
+    }
+    if (m[1]) {
+        const int b = __builtin_ctz(m[1]);
+        m[1] &= m[1] - 1u;
+        return 32 + b;
+    }
+    if (m[2]) {
+        const int b = __builtin_ctz(m[2]);
+        m[2] &= m[2] - 1u;
+        return 64 + b;
+    }
+    if (m[3]) {
+        const int b = __builtin_ctz(m[3]);
+        m[3] &= m[3] - 1u;
+        return 96 + b;
+    }
+    return -1;
+}
+
+// One exceptional bond (k) of the node whose values are given: closed-form
+// stretch, damage history and damage law.  A bond's largest stretch is kept in
+// hist once it passes the bond's limit stretch (never decreasing, so damage
+// never heals); `was` says the bond had passed it before (its bit in the
+// node's damage mask), and *now is set when it passes it for the first time.
+// Returns false for a ghost neighbour, which contributes nothing.
+template <typename T, bool HAS_C, typename Src>
+__device__ __forceinline__ bool exc_bond(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
+                                         const T *__restrict__ S0, T *__restrict__ Hs, const T *__restrict__ Gp,
+                                         int gstep, uint32_t lb1, uint32_t lbh, const typename Vec4<T>::t &ui, T s0i,
+                                         T ci, T gi, int k, bool was, bool &now, T &fx, T &fy, T &fz)
 {
     using V4 = typename Vec4<T>::t;
-    const uint32_t lbh = (uint32_t)node * (uint32_t)sizeof(T);
-#pragma unroll
-    for (int wd = 0; wd < 4; ++wd) {
-        uint32_t bits = todo[wd];
-        while (bits) {
-            const int b = __builtin_ctz(bits);
-            bits &= bits - 1u;
-            const int k = 32 * wd + b;
-            const uint32_t e = tab.slot[k];
-            const int x = (int)(e & 15u) - 3, y = (int)((e >> 4) & 15u) - 3, z = (int)((e >> 8) & 15u) - 3;
-            const int len2 = (int)(e >> 12);
-            const V4 uj = src.get(x, y, z);
-            if (uj.w == T(0)) continue;
-            const int64_t off = (int64_t)x + (int64_t)y * a.PX + (int64_t)z * a.PXY;
-            T ex, ey, ez, ry;
-            const T num = num_rt<T>(ui, uj, x, y, z, ex, ey, ez);
-            const T s = stretch_from_num(num, T(len2), tab.len[len2], ry);
-            const T s0b = T(0.5) * (s0i + ld(S0, off, lb1));
-            const uint32_t bit = 1u << b;
-            T *H = (T *)((char *)(Hs + (int64_t)k * a.M) + lbh);
-            T kap = (dm[wd] & bit) ? *H : T(0);
-            if (s > kap && s > s0b) {
-                kap = s;
-                *H = s;
-                dm[wd] |= bit;
+    const uint32_t e = tab.slot[k];
+    const int x = (int)(e & 15u) - 3, y = (int)((e >> 4) & 15u) - 3, z = (int)((e >> 8) & 15u) - 3;
+    const int len2 = (int)(e >> 12);
+    const V4 uj = src.get(x, y, z);
+    now = false;
+    if (uj.w == T(0)) return false;
+    const int64_t off = (int64_t)x + (int64_t)y * a.PX + (int64_t)z * a.PXY;
+    T ex, ey, ez, ry;
+    const T num = num_rt<T>(ui, uj, x, y, z, ex, ey, ez);
+    const T s = stretch_from_num(num, T(len2), tab.len[len2], ry);
+    const T s0b = T(0.5) * (s0i + ld(S0, off, lb1));
+    T *H = (T *)((char *)(Hs + (int64_t)k * a.M) + lbh);
+    T kap = was ? *H : T(0);
+    if (s > kap && s > s0b) {
+        kap = s;
+        *H = s;
+        now = true;
+    }
+    T cb = T(1);
+    if constexpr (HAS_C) cb = T(0.5) * (ci + src.getc(x, y, z));
+    T keep = T(1);
+    if (kap > s0b) {
+        // bond fracture energy: endpoint mean, as for s0 and c
+        const T gb = T(0.5) * (gi + ld(Gp, off * gstep, lb1 * (uint32_t)gstep));
+        const T sc = s0b + quot(a.gamma_rel * gb, cb * s0b);
+        keep = keep_fraction(a, kap, s0b, sc);
+    }
+    const T w = keep * s * ry * cb;
+    fx = w * (T(x) + ex);
+    fy = w * (T(y) + ey);
+    fz = w * (T(z) + ez);
+    return true;
+}
+
+// The bonds the masked fast loop left out (todo = its exceptions minus the
+// notch-cut bonds), for every node of the wavefront at once.  Nodes near a
+// crack own many such bonds and their neighbours few; a walk of each lane
+// over its own bonds would take as many rounds as the busiest lane, with most
+// lanes idle.  Instead, round r takes the r-th bond (in slot order) of every
+// node that has more than r, consecutive rounds are packed into a list of up
+// to 64 bonds, and the list is evaluated one bond per lane with the owning
+// node's values fetched across lanes.  Each owner then adds its results round
+// by round, i.e. in slot order, so a node's force is bit-identical to a walk
+// over its own bonds.  Called by every lane of the wave (lanes without a node
+// pass todo = 0); list is this wave's 64-entry slice of block-shared memory.
+template <typename T, bool KAHAN, bool HAS_C, typename Src>
+__device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
+                                         const T *__restrict__ S0, T *__restrict__ Hs, const T *__restrict__ Gp,
+                                         int gstep, uint32_t p, uint32_t node, const typename Vec4<T>::t &ui,
+                                         T s0i, T ci, T gi, const uint32_t (&todo)[4], uint32_t (&dm)[4],
+                                         Acc3<T, KAHAN> &acc, uint16_t *list)
+{
+    using V4 = typename Vec4<T>::t;
+    const uint32_t lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t cnt = __builtin_popcount(todo[0]) + __builtin_popcount(todo[1]) + __builtin_popcount(todo[2]) +
+                         __builtin_popcount(todo[3]);
+    uint32_t rem[4] = {todo[0], todo[1], todo[2], todo[3]};
+    const uint32_t key = src.key();
+    uint32_t r = 0;
+    while (__any(cnt > r)) {
+        // list rounds r0 .. r - 1 (at least one: a round has at most 64 bonds)
+        const uint32_t r0 = r;
+        uint32_t walk[4] = {rem[0], rem[1], rem[2], rem[3]};
+        uint32_t fill = 0;
+        for (;;) {
+            const uint64_t m = __ballot(cnt > r);
+            const uint32_t n = (uint32_t)__popcll(m);
+            if (n == 0 || fill + n > 64u) break;
+            if (cnt > r) {
+                const int k = pop_slot(rem);
+                const uint32_t at = fill + (uint32_t)__popcll(m & below);
+                list[at] = (uint16_t)(lane << 8 | (mask_bit(dm, k) ? 128u : 0u) | (uint32_t)k);
             }
-            T cb = T(1);
-            if constexpr (HAS_C) cb = T(0.5) * (ci + src.getc(x, y, z));
-            T keep = T(1);
-            if (kap > s0b) {
-                // bond fracture energy: endpoint mean, as for s0 and c
-                const T gb = T(0.5) * (gi + ld(Gp, off * gstep, lb1 * (uint32_t)gstep));
-                const T sc = s0b + quot(a.gamma_rel * gb, cb * s0b);
-                keep = keep_fraction(a, kap, s0b, sc);
-            }
-            const T w = keep * s * ry * cb;
-            acc.add(w * (T(x) + ex), w * (T(y) + ey), w * (T(z) + ez));
+            fill += n;
+            ++r;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // one listed bond per lane
+        const bool has = lane < fill;
+        const uint32_t ent = has ? list[lane] : (lane << 8);
+        const uint32_t o = ent >> 8;
+        V4 oui;
+        oui.x = shfl_t(ui.x, o);
+        oui.y = shfl_t(ui.y, o);
+        oui.z = shfl_t(ui.z, o);
+        oui.w = T(1);
+        const T os0 = shfl_t(s0i, o);
+        const T oci = HAS_C ? shfl_t(ci, o) : T(1);
+        const T ogi = shfl_t(gi, o);
+        const uint32_t op = shfl_u32(p, o), onode = shfl_u32(node, o), okey = shfl_u32(key, o);
+        T fx = T(0), fy = T(0), fz = T(0);
+        bool now = false, live = false;
+        if (has)
+            live = exc_bond<T, HAS_C>(a, src.rebased(okey), tab, S0, Hs, Gp, gstep, op * (uint32_t)sizeof(T),
+                                      onode * (uint32_t)sizeof(T), oui, os0, oci, ogi, (int)(ent & 127u),
+                                      (ent & 128u) != 0u, now, fx, fy, fz);
+        const uint32_t flags = (live ? 1u : 0u) | (now ? 2u : 0u);
+        // owners add their results round by round
+        uint32_t base = 0;
+        for (uint32_t rr = r0; rr < r; ++rr) {
+            const uint64_t m = __ballot(cnt > rr);
+            const bool mi = cnt > rr;
+            const uint32_t srcl = mi ? base + (uint32_t)__popcll(m & below) : lane;
+            const T vx = shfl_t(fx, srcl), vy = shfl_t(fy, srcl), vz = shfl_t(fz, srcl);
+            const uint32_t fl = shfl_u32(flags, srcl);
+            if (mi) {
+                const int k = pop_slot(walk);
+                if (fl & 1u) acc.add(vx, vy, vz);
+                if (fl & 2u) set_mask_bit(dm, k);
+            }
+            base += (uint32_t)__popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -628,9 +785,8 @@ __device__ __forceinline__ void kick_drift(const StepParams<T> &a, T G, T &vh, T
 // sum runs in a fixed order (a strided pass over 64 lanes, then a fixed
 // tree), so R depends neither on scheduling nor on the block size.
 template <typename T, int NT>
-__device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int sample, int64_t n)
+__device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int sample, int64_t n, double *part)
 {
-    __shared__ double part[64];
     const int64_t prev = n - 1;
     const double *rf = a.rf + ((int64_t)(prev & 1) * a.rf_stride) + (int64_t)sample * a.nsup;
     if (threadIdx.x < 64) {
@@ -654,18 +810,23 @@ __device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int samp
     }
 }
 
-// Forces and Verlet update of one node, given its neighbour source.
+// Forces and Verlet update of one node, given its neighbour source.  Every
+// lane of the wavefront calls it (the exception pass works across lanes);
+// lanes past the mesh edge pass valid = false and only help that pass.
 template <typename T, bool KAHAN, bool HAS_C, bool PLANE, typename Src>
 __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab, int sample,
-                                          int64_t n, int64_t node, int64_t p, const typename Vec4<T>::t &ui)
+                                          int64_t n, int64_t node, int64_t p, const typename Vec4<T>::t &ui,
+                                          bool valid, uint16_t *list)
 {
     using V4 = typename Vec4<T>::t;
     const T *__restrict__ S0 = a.s0pad + (int64_t)sample * a.P;
     const T *__restrict__ Cp = HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr;
-    const uint32_t lb1 = (uint32_t)p * (uint32_t)sizeof(T);
     const int64_t sm = (int64_t)sample * a.M + node;
-    const NodeInfo inf = a.info[node];
-    const T ci = HAS_C ? Cp[p] : T(1);
+    const NodeInfo inf = valid ? a.info[node] : NodeInfo{-1, -1};
+    const T ci = (HAS_C && valid) ? Cp[p] : T(1);
+    // without a fracture-energy field every bond reads the one unit value
+    const int gstep = a.gstep;
+    const T *__restrict__ Gp = a.gpad + (int64_t)sample * a.P * gstep;
 
     Acc3<T, KAHAN> acc;
     acc.zero();
@@ -677,42 +838,51 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
     // FP64 evaluates the closed form on both paths and always takes the
     // masked one.
     const bool is_cut = inf.cut >= 0;
-    const bool sticky = ui.w < T(0);
-    T thr = a.thr[sm];
-    if constexpr (sizeof(T) == 4) thr = fmin(thr, T(kSeriesBound));
+    const bool sticky = valid && ui.w < T(0);
     bool masked = sizeof(T) == 8 || __any(is_cut || sticky) != 0;
-    if constexpr (sizeof(T) == 4) {
-        if (!masked) {
-            const uint32_t none[4] = {0u, 0u, 0u, 0u};
-            uint32_t unused[4] = {0u, 0u, 0u, 0u};
-            bool flag = false;
-            fast_loop<T, KAHAN, HAS_C, false, PLANE>(a, src, ui, ci, thr, acc, flag, none, unused);
-            if (flag) {
-                acc.zero();
-                masked = true;
+    bool dirty = sticky;
+    uint4 d0 = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t todo[4] = {0u, 0u, 0u, 0u};
+    if (valid) {
+        T thr = a.thr[sm];
+        if constexpr (sizeof(T) == 4) thr = fmin(thr, T(kSeriesBound));
+        if constexpr (sizeof(T) == 4) {
+            if (!masked) {
+                const uint32_t none[4] = {0u, 0u, 0u, 0u};
+                uint32_t unused[4] = {0u, 0u, 0u, 0u};
+                bool flag = false;
+                fast_loop<T, KAHAN, HAS_C, false, PLANE>(a, src, ui, ci, thr, acc, flag, none, unused);
+                if (flag) {
+                    acc.zero();
+                    masked = true;
+                }
             }
         }
+        if (masked) {
+            const uint4 cm = is_cut ? a.cut[inf.cut] : make_uint4(0u, 0u, 0u, 0u);
+            if (sticky) d0 = a.dmask[sm];
+            const uint32_t skip[4] = {cm.x | d0.x, cm.y | d0.y, cm.z | d0.z, cm.w | d0.w};
+            uint32_t exc[4] = {0u, 0u, 0u, 0u};
+            bool unused = false;
+            fast_loop<T, KAHAN, HAS_C, true, PLANE>(a, src, ui, ci, thr, acc, unused, skip, exc);
+            todo[0] = exc[0] & ~cm.x;
+            todo[1] = exc[1] & ~cm.y;
+            todo[2] = exc[2] & ~cm.z;
+            todo[3] = exc[3] & ~cm.w;
+            dirty = dirty || ((exc[0] | exc[1] | exc[2] | exc[3]) != 0u);
+        }
     }
-    bool dirty = sticky;
-    if (masked) {
-        const uint4 cm = is_cut ? a.cut[inf.cut] : make_uint4(0u, 0u, 0u, 0u);
-        const uint4 d0 = sticky ? a.dmask[sm] : make_uint4(0u, 0u, 0u, 0u);
-        const uint32_t skip[4] = {cm.x | d0.x, cm.y | d0.y, cm.z | d0.z, cm.w | d0.w};
-        uint32_t exc[4] = {0u, 0u, 0u, 0u};
-        bool unused = false;
-        fast_loop<T, KAHAN, HAS_C, true, PLANE>(a, src, ui, ci, thr, acc, unused, skip, exc);
-        const uint32_t todo[4] = {exc[0] & ~cm.x, exc[1] & ~cm.y, exc[2] & ~cm.z, exc[3] & ~cm.w};
-        uint32_t dm[4] = {d0.x, d0.y, d0.z, d0.w};
+    uint32_t dm[4] = {d0.x, d0.y, d0.z, d0.w};
+    if (__any((todo[0] | todo[1] | todo[2] | todo[3]) != 0u)) {
         T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
-        // without a fracture-energy field every bond reads the one unit value
-        const int gstep = a.gstep;
-        const T *__restrict__ Gp = a.gpad + (int64_t)sample * a.P * gstep;
-        exc_loop<T, KAHAN, HAS_C>(a, src, tab, S0, Hs, lb1, node, ui, S0[p], ci, Gp, gstep, ld(Gp, p * gstep, 0u),
-                                  todo, dm, acc);
-        if (dm[0] != d0.x || dm[1] != d0.y || dm[2] != d0.z || dm[3] != d0.w)
-            a.dmask[sm] = make_uint4(dm[0], dm[1], dm[2], dm[3]);
-        dirty = dirty || ((exc[0] | exc[1] | exc[2] | exc[3]) != 0u);
+        const T s0i = valid ? S0[p] : T(1);
+        const T gi = valid ? ld(Gp, p * gstep, 0u) : T(1);
+        exc_pool<T, KAHAN, HAS_C>(a, src, tab, S0, Hs, Gp, gstep, (uint32_t)p, (uint32_t)node, ui, s0i, ci, gi, todo,
+                                  dm, acc, list);
     }
+    if (!valid) return;
+    if (dm[0] != d0.x || dm[1] != d0.y || dm[2] != d0.z || dm[3] != d0.w)
+        a.dmask[sm] = make_uint4(dm[0], dm[1], dm[2], dm[3]);
     if (a.force_only) {
         double *L = a.L_out + 3 * sm;
         L[0] = a.LV * ((double)acc.x - (KAHAN ? (double)acc.cx : 0.0));
@@ -773,13 +943,17 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
     __shared__ V4 tile[LDS ? BR::TILE : 1];
     __shared__ T ctile[(LDS && HAS_C) ? BR::TILE : 1];
     __shared__ SlotLds<T> tab;
+    // the previous reaction's partial sums, then each wave's exception list
+    __shared__ double scratch[64];
+    static_assert(BR::N <= 256, "one 64-entry exception list per wave in 512 bytes");
+    uint16_t *list = (uint16_t *)scratch + 64 * (threadIdx.x / 64);
     const int64_t per_xcd = gridDim.x / kXcds;
     const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
     if (item >= a.n_items) return;
     const int sample = (int)(item / a.tiles);
     const int64_t t = item % a.tiles;
     const int64_t n = a.step_base[sample] + a.k_local;
-    if (!a.force_only && t == 0 && n >= 1 && n <= a.n_steps) reduce_previous<T, BR::N>(a, sample, n);
+    if (!a.force_only && t == 0 && n >= 1 && n <= a.n_steps) reduce_previous<T, BR::N>(a, sample, n, scratch);
     if (!a.force_only && n >= a.n_steps) return;   // whole block: finished sample
     const V4 *__restrict__ U = a.u_cur + (int64_t)sample * a.P;
     fill_slot_lds(tab);
@@ -803,16 +977,16 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         __syncthreads();
         const int tx = threadIdx.x % BR::BX, ty = (threadIdx.x / BR::BX) % BR::BY, tz = threadIdx.x / (BR::BX * BR::BY);
         const int ix = x0 + tx, iy = y0 + ty, iz = z0 + tz;
-        if (ix >= a.nx || iy >= a.ny || iz >= a.nz) return;
-        const int64_t node = ix + (int64_t)a.nx * (iy + (int64_t)a.ny * iz);
-        const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
+        const bool valid = ix < a.nx && iy < a.ny && iz < a.nz;
+        const int64_t node = valid ? ix + (int64_t)a.nx * (iy + (int64_t)a.ny * iz) : 0;
+        const int64_t p = valid ? (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY : 0;
         const int c = (tx + kHalo) + BR::LX * (ty + YH) + BR::LXY * (tz + kHalo);
         const LdsSrc<T, BR> src{tile, ctile, c};
-        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, tile[c]);
+        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, tile[c], valid, list);
     } else {
         __syncthreads();
-        const int64_t node = t * BR::N + threadIdx.x;
-        if (node >= a.M) return;
+        const bool valid = t * BR::N + threadIdx.x < a.M;
+        const int64_t node = valid ? t * BR::N + threadIdx.x : 0;
         const uint32_t nd = (uint32_t)node, nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
         const uint32_t r = nd / nx;
         const int ix = (int)(nd - r * nx);
@@ -821,7 +995,7 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
         const GlobalSrc<T> src{U, (uint32_t)p * (uint32_t)sizeof(V4), a.PX, a.PXY,
                                HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr, (uint32_t)p * (uint32_t)sizeof(T)};
-        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, U[p]);
+        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, U[p], valid, list);
     }
 }
 
