@@ -207,6 +207,25 @@ def plane_leg(samples=(2152, 567, 204, 67, 18)):
             "multilevel_quantiles_N": {str(k): float(v) for k, v in zip(u, quant)}}
 
 
+def plane_adaptive_leg(eps=50.0, n_warm=100):
+    """Algorithm 1 on the plane-stress Specimen 3 (five levels, the paper's
+    material model, 100 warm-up samples per level as in the paper, refinement
+    ratio 4 between 2D levels, fitted alpha) at RMSE target eps (N)."""
+    import workloads as W
+    from paper_2212_04415_amd import mlmc
+    levels = [W.level2d(l) for l in range(5)]
+    run, costs, dofs = mlmc.solver_sampler(levels, seed=6, precision="f32", corr_len=20e-3, n_modes=W.FIELD_MODES,
+                                           mean=W.S0_MEAN, cov=W.FIELD_COV, kl_coefficients=W.kl_coefficients,
+                                           field_model="paper")
+    out = mlmc.adaptive(run, eps, costs, dofs, n_warm=n_warm, alpha=None, alpha_default=0.5, refinement=4.0)
+    return {"eps_N": eps, "levels_used": out["L"] + 1, "converged": out["converged"], "N": out["N"],
+            "estimate_N": out["estimate"], "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "bias_estimate_N": out["bias"], "alpha_fitted": out["history"][-1]["alpha"],
+            "level_means_N": [m for m, _, _ in out["levels"]],
+            "wall_s": out["wall_s"], "bond_updates_per_s": out["cost"] / out["wall_s"],
+            "mlmc_samples_per_s": sum(out["N"]) / out["wall_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +244,8 @@ def main():
                     help="also time the size-sweep beams (D = 50..400 mm, 32 samples, first 1000 steps)")
     ap.add_argument("--plane", action="store_true",
                     help="also run the plane-stress Specimen-3 MLMC hierarchy (five levels, paper material model)")
+    ap.add_argument("--plane-adaptive", action="store_true",
+                    help="also run the adaptive MLMC algorithm on the plane-stress Specimen 3 (RMSE target 50 N)")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="profiling only: time steps per batch solve (default: the workload's 8000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -357,6 +378,8 @@ def main():
         line["size_sweep"] = sweep_leg()
     if args.plane:
         line["plane_stress_mlmc"] = plane_leg()
+    if args.plane_adaptive:
+        line["plane_stress_mlmc_adaptive"] = plane_adaptive_leg()
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

@@ -78,7 +78,11 @@ def cost_exponents(alpha, beta, gamma):
 
 
 def bias_bound(y_last, alpha, refinement, r=1.0):
-    return abs(y_last) / (r * refinement ** alpha - 1.0)
+    """Eq. bias_error.  It bounds the bias only for a positive rate
+    (r m^alpha > 1); otherwise (a fitted rate at or below zero: the
+    corrections do not decay) the bias is unbounded: +inf."""
+    den = r * refinement ** alpha - 1.0
+    return abs(y_last) / den if den > 0 else float("inf")
 
 
 def fit_rate(x, y):

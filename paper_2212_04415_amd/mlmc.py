@@ -108,33 +108,45 @@ def fit_rate(x, y):
 
 
 def solver_sampler(levels: Sequence, seed: int, *, precision: str = "f32", corr_len: float, n_modes: int,
-                   mean: float, cov: float, kl_coefficients, n_quad: int = 256, stream=None):
+                   mean: float, cov: float, kl_coefficients, n_quad: int = 256, stream=None,
+                   field_model: str = "lognormal"):
     """A sampler for `adaptive` backed by the batched solver: run(requests)
     with requests {level: (start, count)} runs, in one pd_run_batch call, the
     level-l samples start .. start+count-1 (KL coefficients of stream l) and,
     for l > 0, their coarse partners on the level l-1 mesh with the same
     coefficients, and returns {level: (q_fine, q_coarse or None)} as device
     FP64 tensors.  Also returns the per-sample costs (bond updates, fine plus
-    coarse) and the node counts."""
+    coarse) and the node counts.  field_model as in coupled_batch."""
     import torch
     meshes = [B.Mesh.for_level(lv) for lv in levels]
-    kls = [B.KL(m, corr_len, n_modes, n_quad) for m in meshes]
+    if field_model == "lognormal":
+        kls = [B.KL(m, corr_len, n_modes, n_quad) for m in meshes]
+    elif field_model == "paper":
+        base = B.KL.exponential(meshes[0], corr_len, n_modes)
+        kls = [base] + [base.extend(m) for m in meshes[1:]]
+        n_modes = base.n_modes
+    else:
+        raise ValueError(f"unknown field model {field_model!r}")
     dtype = torch.float32 if precision == "f32" else torch.float64
     params = [B.make_params(lv, precision=precision) for lv in levels]
     work = [m.n_bonds * lv.n_steps for m, lv in zip(meshes, levels)]
     costs = [work[l] + (work[l - 1] if l > 0 else 0) for l in range(len(levels))]
     dofs = [3 * m.n_nodes for m in meshes]
 
+    def item(l, xi, count):
+        if field_model == "lognormal":
+            return B.BatchItem(meshes[l], params[l], count, kls[l].lognormal(xi, mean, cov, dtype=dtype, stream=stream))
+        s0, c, gf = B.fib_fields(meshes[l], kls[l].gaussian(xi, stream=stream), dtype=dtype, stream=stream)
+        return B.BatchItem(meshes[l], params[l], count, s0, c, gf)
+
     def run(requests: Dict[int, Tuple[int, int]]):
         items, owners = [], []
         for l, (start, count) in sorted(requests.items()):
             xi = torch.tensor(kl_coefficients(seed, start + count, n_modes, stream=l)[start:])
-            items.append(B.BatchItem(meshes[l], params[l], count,
-                                     kls[l].lognormal(xi, mean, cov, dtype=dtype, stream=stream)))
+            items.append(item(l, xi, count))
             owners.append((l, "fine"))
             if l > 0:
-                items.append(B.BatchItem(meshes[l - 1], params[l - 1], count,
-                                         kls[l - 1].lognormal(xi, mean, cov, dtype=dtype, stream=stream)))
+                items.append(item(l - 1, xi, count))
                 owners.append((l, "coarse"))
         outs = B.run_batch(items, stream=stream)
         res: Dict[int, list] = {}
@@ -206,7 +218,9 @@ def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[f
             a = -fit_rate(dofs[1:L + 1], means[1:L + 1])[0]
         else:
             a = alpha_default
-        b = bias(means[L], a, refinement, r)
+        # Eq. bias_error needs a positive rate; corrections that do not decay
+        # (fitted alpha <= 0) leave the bias unbounded
+        b = bias(means[L], a, refinement, r) if r * refinement ** a > 1.0 else float("inf")
         history.append(dict(L=L, V=list(V), n_hat=[int(v) for v in n_hat], N=list(N), alpha=a, bias=b))
         if b < eps_b:
             converged = True

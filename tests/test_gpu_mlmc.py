@@ -136,6 +136,25 @@ def test_adaptive_with_the_solver_reproduces_the_fixed_hierarchy():
         assert np.allclose(a, b, rtol=1e-12)
 
 
+def test_adaptive_on_the_plane_specimen_with_the_paper_material():
+    """Algorithm 1 on the plane-stress Specimen 3 (levels 0-1, refinement
+    ratio 4 in 2D) with the paper's material model: its samples are the
+    fixed hierarchy's (same coefficient streams, same planar field basis)."""
+    from paper_2212_04415_amd import mlmc as PM
+    levels = [W.level2d(0), W.level2d(1)]
+    kw = dict(precision="f32", corr_len=20e-3, n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
+              kl_coefficients=W.kl_coefficients, field_model="paper")
+    run, costs, dofs = PM.solver_sampler(levels, seed=7, **kw)
+    out = PM.adaptive(run, 100.0, costs, dofs, n_warm=8, alpha=0.5, refinement=4.0)
+    assert out["L"] == 1 and out["N"][0] >= 8
+    for h in out["history"]:
+        assert all(n >= nh for n, nh in zip(h["N"], h["n_hat"]))
+    fixed = PM.coupled_batch(levels, out["N"], seed=7, **kw)
+    assert fixed["estimate"] == pytest.approx(out["estimate"], rel=1e-12)
+    for a, b in zip(fixed["sums"], out["sums"]):
+        assert np.allclose(a, b, rtol=1e-12)
+
+
 # ------------------------------------------------------------------ multilevel CDF
 @pytest.mark.parametrize("sizes", [(1000, 137, 17), (1,), (5, 5), (64, 1, 3)])
 def test_multilevel_cdf_matches_the_oracle(sizes):

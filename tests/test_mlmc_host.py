@@ -108,6 +108,23 @@ def test_oracle_adaptive_on_deterministic_differences():
     assert out["L"] == 1 and not out["converged"]
 
 
+def test_non_decaying_corrections_leave_the_bias_unbounded():
+    """Eq. bias_error bounds the bias only for r m^alpha > 1.  Corrections
+    that grow with the level fit a negative rate: the bias estimate is
+    infinite and the algorithm refines to the last level without converging,
+    in the oracle and in the GPU driver's own rule alike."""
+    assert OM.bias_bound(50.0, -0.2, 4.0) == float("inf")
+    assert OM.bias_bound(50.0, 0.0, 4.0) == float("inf")
+    assert OM.bias_bound(50.0, 0.5, 4.0) == pytest.approx(50.0)
+    c = 100.0
+    sampler = lambda l, start, count: np.full(count, c * 2.0 ** l)      # |Y_l| grows
+    costs = [4.0 ** l for l in range(4)]
+    dofs = [350.0 * 4 ** l for l in range(4)]
+    out = OM.adaptive(sampler, 100.0, costs, dofs, n_warm=3, alpha=None, alpha_default=0.5, refinement=4.0)
+    assert out["L"] == 3 and not out["converged"]
+    assert out["history"][-1]["alpha"] < 0 and out["history"][-1]["bias"] == float("inf")
+
+
 def test_oracle_adaptive_allocation_meets_the_sampling_budget():
     """Gaussian level differences: after each iteration every level holds at
     least its allocation, the reported sampling variance is sum V_l / N_l of
