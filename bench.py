@@ -185,6 +185,7 @@ def plane_leg(samples=(2152, 567, 204, 67, 18)):
     sample paired with a coarse solve on the same coefficients, one batched
     FP32 call.  The sample counts are the paper's allocation for this
     specimen at a sampling tolerance of 10 N (section 6.2)."""
+    import numpy as np
     import torch
     import workloads as W
     from paper_2212_04415_amd import mlmc
@@ -199,7 +200,15 @@ def plane_leg(samples=(2152, 567, 204, 67, 18)):
                        for l in range(1, L)]
     u = [0.05, 0.5, 0.95]
     quant = mlmc.cdf(fine, coarse, u)
+    # standard Monte Carlo at the same sampling tolerance (Eq. MC_num_samples):
+    # N = V[Q_L] / eps_s^2 solves of the finest level, V from its fine samples
+    eps_s = 10.0
+    qL = np.asarray(out["Q"][L - 1][:samples[L - 1]])
+    n_mc = float(np.var(qL, ddof=1)) / eps_s ** 2
+    mc_cost = n_mc * out["bonds"][L - 1] * out["steps"][L - 1]
     return {"workload": "specimen3_plane_stress_paper_material", "nodes": out["nodes"], "bonds": out["bonds"],
+            "mc_equivalent": {"eps_s_N": eps_s, "N": n_mc, "bond_updates": mc_cost,
+                              "mlmc_bond_updates": bu, "cost_ratio_mc_over_mlmc": mc_cost / bu},
             "steps": out["steps"], "solves_per_level": out["solves"], "wall_s": out["wall_s"],
             "bond_updates_per_s": bu / out["wall_s"], "mlmc_samples_per_s": sum(samples) / out["wall_s"],
             "estimate_N": out["estimate"], "sampling_std_N": out["sampling_variance"] ** 0.5,
