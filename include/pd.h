@@ -77,11 +77,14 @@ typedef struct pd_kl_s *pd_kl;
  * x = extent[0]/2 -+ span/2; the load pad is one block on the top face centred
  * on x = extent[0]/2; every pad spans the whole thickness.  notch_depth > 0
  * cuts every bond crossing the plane x = extent[0]/2 below that height.
- * thickness = 0: a 3D body.  thickness > 0: a plane-stress body of that
- * thickness (appendix A, Eq. bond_stiffness_constant: c = 9E / (pi t delta^3);
- * nodal volume dx^2 t; critical stretch from Eq. exp_fracture_energy_2D),
- * represented with one node through the thickness (extent[1] = dx): every
- * out-of-plane neighbour is absent, so the 28 in-plane bonds remain. */
+ * thickness = 0: a 3D body.  thickness > 0: a plane body of that thickness
+ * (appendix A: nodal volume dx^2 t; critical stretch from
+ * Eq. exp_fracture_energy_2D), in plane stress (plane_strain = 0,
+ * Eq. bond_stiffness_constant: c = 9E / (pi t delta^3)) or plane strain
+ * (plane_strain = 1: c = 48E / (5 pi t delta^3)), represented with one node
+ * through the thickness (extent[1] = dx): every out-of-plane neighbour is
+ * absent, so the 28 in-plane bonds remain.  plane_strain must be 0 for a 3D
+ * body (PD_EINVAL otherwise). */
 typedef struct {
     double extent[3];
     double dx;
@@ -90,6 +93,7 @@ typedef struct {
     double notch_depth;
     double pad_width;
     double thickness;
+    int32_t plane_strain;
 } pd_mesh_desc;
 
 /* Material, loading and numerics of a run.
@@ -303,8 +307,9 @@ PD_API int pd_kl_gaussian(pd_kl kl, const double *xi_dev, int64_t n_samples, dou
  * relations the paper cites: E = alpha_E 21.5 GPa (f_c / 10 MPa)^(1/3),
  * f_t = 0.3 MPa (f_ck / MPa)^(2/3) with f_ck = max(f_c - delta_f, fck_min),
  * G_F = 73 N/m (f_c / MPa)^0.18.  Per node: s0 = f_t / E, c = 12 E / (pi
- * delta^4) with the mesh's horizon (a plane-stress mesh of thickness t:
- * c = 9 E / (pi t delta^3), appendix A), G_F.  All in SI. */
+ * delta^4) with the mesh's horizon (a plane mesh of thickness t:
+ * c = 9 E / (pi t delta^3) in plane stress, 48 E / (5 pi t delta^3) in plane
+ * strain, appendix A), G_F.  All in SI. */
 typedef struct {
     double fcm;        /* mean compressive strength, Pa (paper: 42.3e6) */
     double weibull_m;  /* Weibull modulus (paper: 3) */

@@ -140,13 +140,18 @@ def fib_properties(fc, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6):
     return E, ft, GF
 
 
-def material_fields(g, delta, fcm=42.3e6, m=3.0, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6, thickness=0.0):
+def material_fields(g, delta, fcm=42.3e6, m=3.0, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6, thickness=0.0,
+                    plane_strain=False):
     """Per-node (s0, c, G_F) from a standard-normal Gaussian field g; c in
-    the 3D form, or the plane-stress form 9 E / (pi t delta^3) of appendix A
-    (Eq. bond_stiffness_constant) for a body of thickness t > 0."""
+    the 3D form, or for a body of thickness t > 0 the plane-stress form
+    9 E / (pi t delta^3) or plane-strain form 48 E / (5 pi t delta^3) of
+    appendix A (Eq. bond_stiffness_constant)."""
     fc = weibull_from_gaussian(g, fcm, m)
     E, ft, GF = fib_properties(fc, alpha_E, delta_f, fck_min)
-    c = 9.0 * E / (np.pi * thickness * delta ** 3) if thickness > 0 else 12.0 * E / (np.pi * delta ** 4)
+    if thickness > 0:
+        c = (48.0 / 5.0 if plane_strain else 9.0) * E / (np.pi * thickness * delta ** 3)
+    else:
+        c = 12.0 * E / (np.pi * delta ** 4)
     return ft / E, c, GF
 
 

@@ -104,6 +104,11 @@ def micromodulus_plane_stress(E, delta, t):
     return 9.0 * E / (np.pi * t * delta ** 3)
 
 
+def micromodulus_plane_strain(E, delta, t):
+    """Appendix A, Eq. bond_stiffness_constant (plane strain)."""
+    return 48.0 * E / (5.0 * np.pi * t * delta ** 3)
+
+
 def damage(law, kappa, s0, sc, k, alpha):
     return lib().pdo_damage(law, kappa, s0, sc, k, alpha)
 
@@ -243,7 +248,12 @@ def beam_problem(level, s0=None, c=None, *, E=None, rho=None, GF=None, damping=N
     M = int(np.prod(shape))
     delta = m_ratio * dx
     s0 = np.full(M, W.S0_MEAN) if s0 is None else np.asarray(s0, dtype=np.float64)
-    c_ref = micromodulus_plane_stress(E, delta, beam.thickness) if plane else micromodulus(E, delta)
+    if not plane:
+        c_ref = micromodulus(E, delta)
+    elif getattr(beam, "plane_strain", False):
+        c_ref = micromodulus_plane_strain(E, delta, beam.thickness)
+    else:
+        c_ref = micromodulus_plane_stress(E, delta, beam.thickness)
     c = np.full(M, c_ref) if c is None else np.asarray(c, dtype=np.float64)
     return Problem(shape=shape, dx=dx, bond_i=bi, bond_j=bj, xi=v.astype(np.float64) * dx,
                    support=sup, load=load, s0=s0, c=c, rho=rho, damping=damping,

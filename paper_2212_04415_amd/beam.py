@@ -26,7 +26,8 @@ class Mesh:
         plane = getattr(beam, "plane", False)
         desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, dx if plane else beam.thickness, beam.depth), dx,
                                m_ratio, beam.span, beam.notch_depth, beam.pad_width,
-                               beam.thickness if plane else 0.0)
+                               beam.thickness if plane else 0.0,
+                               1 if plane and getattr(beam, "plane_strain", False) else 0)
         self.h = C.c_void_p()
         pd.pd_build_mesh(C.byref(desc), C.byref(self.h))
         nb = C.c_int64()

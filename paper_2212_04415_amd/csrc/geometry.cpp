@@ -81,7 +81,9 @@ int build_mesh(const pd_mesh_desc *d, pd_mesh_s *m)
     if ((double)n[0] * n[1] * n[2] > 2.0e9) return fail(PD_EINVAL, "mesh too large");
     if (!(d->thickness >= 0)) return fail(PD_EINVAL, "thickness must be >= 0");
     if (d->thickness > 0 && n[1] != 1)
-        return fail(PD_EINVAL, "a plane-stress body has one node through the thickness (extent[1] = dx)");
+        return fail(PD_EINVAL, "a plane body has one node through the thickness (extent[1] = dx)");
+    if (d->plane_strain != 0 && d->plane_strain != 1) return fail(PD_EINVAL, "plane_strain must be 0 or 1");
+    if (d->plane_strain && !(d->thickness > 0)) return fail(PD_EINVAL, "plane strain needs a thickness > 0");
     m->d = *d;
     m->nx = (int)n[0];
     m->ny = (int)n[1];
@@ -200,7 +202,7 @@ int material_from_params(const pd_mesh_s *m, const pd_params *p, Material *out)
     out->delta = m->d.m_ratio * dx;
     // bond stiffness constant (appendix A, Eq. bond_stiffness_constant)
     if (t > 0) {
-        out->c_ref = 9.0 * p->E / (M_PI * t * std::pow(out->delta, 3));   // plane stress
+        out->c_ref = (m->d.plane_strain ? 48.0 / 5.0 : 9.0) * p->E / (M_PI * t * std::pow(out->delta, 3));
         out->volume = dx * dx * t;
     } else {
         out->c_ref = 12.0 * p->E / (M_PI * std::pow(out->delta, 4));      // 3D

@@ -348,9 +348,10 @@ int pd_fib_fields(pd_mesh m, const double *g_dev, int64_t n_samples, const pd_fi
     f.alpha_E = fp->alpha_E;
     f.delta_f = fp->delta_f;
     f.fck_min = fp->fck_min;
-    // micromodulus per unit E: the 3D or the plane-stress form of the mesh
+    // micromodulus per unit E: the 3D, plane-stress or plane-strain form of the mesh
     const double t = m->d.thickness;
-    f.c_scale = t > 0 ? 9.0 / (M_PI * t * delta * delta * delta) : 12.0 / (M_PI * delta * delta * delta * delta);
+    const double k2 = m->d.plane_strain ? 48.0 / 5.0 : 9.0;
+    f.c_scale = t > 0 ? k2 / (M_PI * t * delta * delta * delta) : 12.0 / (M_PI * delta * delta * delta * delta);
     hipStream_t st = (hipStream_t)stream;
     if (out_dtype == PD_DTYPE_F64)
         fib_kernel<double><<<nblocks(n), 256, 0, st>>>(g_dev, n, f, (double *)s0_out, (double *)c_out, (double *)gf_out);

@@ -32,7 +32,7 @@ class PdError(RuntimeError):
 class pd_mesh_desc(C.Structure):
     _fields_ = [("extent", C.c_double * 3), ("dx", C.c_double), ("m_ratio", C.c_double),
                 ("span", C.c_double), ("notch_depth", C.c_double), ("pad_width", C.c_double),
-                ("thickness", C.c_double)]
+                ("thickness", C.c_double), ("plane_strain", C.c_int32)]
 
 
 class pd_params(C.Structure):

@@ -1,10 +1,11 @@
-"""GPU parity of the plane-stress body (appendix A: plane-stress
+"""GPU parity of the plane bodies (appendix A: plane-stress and plane-strain
 micromodulus and the 2D critical stretch; section 6.2: Specimen 3 at the
 levels of Table discretisation, 350 ... 89,600 nodes) with the oracle:
 force evaluations with heterogeneous fields, cracking runs at levels 0-2 in
 FP64 and FP32, every launch shape on the one-node-thick body, and a run
 driven by the paper's material model on the plane."""
 import concurrent.futures as cf
+import dataclasses
 
 import numpy as np
 import pytest
@@ -191,3 +192,40 @@ def test_plane_paper_material_run_matches_oracle(env):
     for k, ref in enumerate(refs):
         assert ref["nstar"] < lv1.n_steps
         assert Q[k].item() == pytest.approx(ref["Q"], rel=5e-3)
+
+
+# ---------------------------------------------------------------- plane strain
+def strain_level(ell):
+    lv = W.level2d(ell)
+    return dataclasses.replace(lv, beam=dataclasses.replace(lv.beam, plane_strain=True))
+
+
+@pytest.mark.parametrize("ell", [0, 1])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_plane_strain_cracking_run_matches_oracle(env, ell, precision):
+    """The plane-strain micromodulus 48E / (5 pi t delta^3) on Specimen 3:
+    peak load and step against the oracle, and a stiffer response than plane
+    stress (the plane-strain micromodulus is 16/15 of the plane-stress one)."""
+    torch, B = env
+    lv = strain_level(ell)
+    ref = S.beam_problem(lv).run(want_state=False)
+    assert 0.2 * lv.n_steps < ref["nstar"] < 0.8 * lv.n_steps
+    out = B.run(B.Mesh.for_level(lv), B.make_params(lv, precision=precision))
+    if precision == "f64":
+        assert out["Q"] == pytest.approx(ref["Q"], rel=1e-9) and out["nstar"] == ref["nstar"]
+    else:
+        assert out["Q"] == pytest.approx(ref["Q"], rel=5e-3)
+        assert abs(out["nstar"] - ref["nstar"]) <= 0.02 * lv.n_steps
+    stress = B.run(B.Mesh.for_level(W.level2d(ell)), B.make_params(W.level2d(ell), precision=precision))
+    assert out["Q"] > stress["Q"]
+
+
+def test_plane_strain_fib_fields(env):
+    torch, B = env
+    lv = strain_level(0)
+    mesh = B.Mesh.for_level(lv)
+    g = np.random.default_rng(3).standard_normal((2, mesh.n_nodes))
+    s0, c, gf = OMAT.material_fields(g, W.M_RATIO * lv.dx, thickness=lv.beam.thickness, plane_strain=True)
+    gs0, gc, ggf = (t.cpu().numpy() for t in B.fib_fields(mesh, torch.tensor(g)))
+    for a, b in ((gs0, s0), (gc, c), (ggf, gf)):
+        assert np.allclose(a, b, rtol=1e-13, atol=0)

@@ -29,10 +29,10 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(pd.SIGNATURES)
 
 
-def build(beam, dx, m_ratio=W.M_RATIO, extent_y=None, thickness=0.0):
+def build(beam, dx, m_ratio=W.M_RATIO, extent_y=None, thickness=0.0, plane_strain=0):
     desc = pd.pd_mesh_desc((C.c_double * 3)(beam.length, beam.thickness if extent_y is None else extent_y,
                                             beam.depth), dx, m_ratio, beam.span, beam.notch_depth, beam.pad_width,
-                           thickness)
+                           thickness, plane_strain)
     h = C.c_void_p()
     rc = pd.lib().pd_build_mesh(C.byref(desc), C.byref(h))
     return rc, h
@@ -142,9 +142,11 @@ def test_host_geometry_plane_specimen_matches_oracle(ell):
         pd.pd_free_mesh(h)
 
 
-@pytest.mark.parametrize("extent_y,thickness", [(2 * 10e-3, 50e-3), (10e-3, -1.0)])
-def test_plane_mesh_rejects_bad_thickness(extent_y, thickness):
-    """A plane body must be one node thick and its thickness non-negative."""
-    rc, h = build(W.SPECIMEN3, 10e-3, extent_y=extent_y, thickness=thickness)
+@pytest.mark.parametrize("extent_y,thickness,strain", [(2 * 10e-3, 50e-3, 0), (10e-3, -1.0, 0), (10e-3, 0.0, 1),
+                                                       (10e-3, 50e-3, 2)])
+def test_plane_mesh_rejects_bad_thickness(extent_y, thickness, strain):
+    """A plane body must be one node thick and its thickness non-negative;
+    plane strain needs a plane body and is a 0/1 flag."""
+    rc, h = build(W.SPECIMEN3, 10e-3, extent_y=extent_y, thickness=thickness, plane_strain=strain)
     assert rc == pd.PD_EINVAL and not h.value
-    assert "thick" in pd.pd_last_error()
+    assert "thick" in pd.pd_last_error() or "plane_strain" in pd.pd_last_error()

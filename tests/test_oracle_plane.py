@@ -27,13 +27,17 @@ E, RHO, T = W.E_MODULUS, W.DENSITY, 50e-3
 K, ALPHA, GF, S0 = W.SOFT_K, W.SOFT_ALPHA, W.FRACTURE_ENERGY, W.S0_MEAN
 
 
-def plane_problem(shape, dx=1e-3, t=T, **kw):
+# (micromodulus, Poisson's ratio of the bond-based solid) per plane model
+MODELS = {"stress": (S.micromodulus_plane_stress, 1.0 / 3.0), "strain": (S.micromodulus_plane_strain, 0.25)}
+
+
+def plane_problem(shape, dx=1e-3, t=T, model="stress", **kw):
     bi, bj, v = G.unique_bonds(shape, W.M_RATIO)
     M = int(np.prod(shape))
     delta = W.M_RATIO * dx
     args = dict(shape=shape, dx=dx, bond_i=bi, bond_j=bj, xi=v * dx,
                 support=np.zeros(0, dtype=np.int64), load=np.zeros(0, dtype=np.int64),
-                s0=np.full(M, S0), c=np.full(M, S.micromodulus_plane_stress(E, delta, t)), rho=RHO,
+                s0=np.full(M, S0), c=np.full(M, MODELS[model][0](E, delta, t)), rho=RHO,
                 damping=0.0, dt=1e-7, du=0.0, n_steps=0, law=S.LAW_TRILINEAR,
                 k=K, alpha=ALPHA, GF=GF, delta=delta, thickness=t)
     args.update(kw)
@@ -89,13 +93,15 @@ def test_specimen3_levels_follow_the_paper_table():
 
 
 # ---------------------------------------------------------------- micromodulus
-def test_isotropic_strain_energy_density():
+@pytest.mark.parametrize("model", ["stress", "strain"])
+def test_isotropic_strain_energy_density(model):
     """u = eps x in plane: every bond has stretch eps and the interior energy
     density (1/2) sum_j (c / 2) eps^2 |xi| V equals the lattice form of the
-    plane-stress continuum value E eps^2 / (1 - nu), nu = 1/3, i.e.
-    3 E eps^2 / 2 times sum_v |v| / (2 pi m^3 / 3)."""
+    continuum value, times sum_v |v| / (2 pi m^3 / 3): in plane stress
+    (nu = 1/3) E eps^2 / (1 - nu) = 3 E eps^2 / 2; in plane strain (nu = 1/4)
+    2 (lambda + mu) eps^2 = E eps^2 / ((1 + nu)(1 - 2 nu)) = 8 E eps^2 / 5."""
     shape, dx, eps = (13, 1, 13), 1e-3, 2e-5
-    p = plane_problem(shape, dx)
+    p = plane_problem(shape, dx, model=model)
     x = G.node_positions(shape, dx)
     u = eps * x
     u[:, 1] = 0.0
@@ -106,7 +112,9 @@ def test_isotropic_strain_energy_density():
     np.add.at(W_node, p.bond_i, 0.5 * w_bond)
     np.add.at(W_node, p.bond_j, 0.5 * w_bond)
     lattice = sum(np.hypot(a, b) for a, b in in_plane_offsets()) / (2 * np.pi * W.M_RATIO ** 3 / 3)
-    cont = 1.5 * E * eps ** 2
+    nu = MODELS[model][1]
+    cont = (E / (1 - nu) if model == "stress" else E / ((1 + nu) * (1 - 2 * nu))) * eps ** 2
+    assert cont == pytest.approx((1.5 if model == "stress" else 1.6) * E * eps ** 2, rel=1e-12)
     Wi = W_node[interior_2d(shape)]
     assert np.allclose(Wi, cont * lattice, rtol=1e-9, atol=0)
     assert lattice == pytest.approx(1.0, abs=0.1)
@@ -115,13 +123,16 @@ def test_isotropic_strain_energy_density():
     assert np.max(np.abs(L[interior_2d(shape)])) < 1e-8 * p.c[0] * eps * p.volume
 
 
-def test_quadratic_field_navier_operator():
+@pytest.mark.parametrize("model", ["stress", "strain"])
+def test_quadratic_field_navier_operator(model):
     """u_x = kappa x^2 / 2: the linearised interior force density is
     c V (kappa / 2) dx sum_v v_x^4 / |v|^3 over in-plane offsets, whose
-    continuum limit is the plane-stress Navier term E / (1 - nu^2) kappa =
-    9 E kappa / 8; no out-of-plane or vertical force."""
+    continuum limit is the Navier term (lambda + 2 mu) kappa: in plane stress
+    E / (1 - nu^2) kappa = 9 E kappa / 8 (nu = 1/3), in plane strain
+    E (1 - nu) / ((1 + nu)(1 - 2 nu)) kappa = 6 E kappa / 5 (nu = 1/4); no
+    out-of-plane or vertical force."""
     shape, dx, kap = (13, 1, 13), 1e-3, 1e-4
-    p = plane_problem(shape, dx)
+    p = plane_problem(shape, dx, model=model)
     x = G.node_positions(shape, dx)
     u = np.zeros_like(x)
     u[:, 0] = 0.5 * kap * x[:, 0] ** 2
@@ -131,7 +142,10 @@ def test_quadratic_field_navier_operator():
     Li = L[interior_2d(shape)]
     assert np.allclose(Li[:, 0], expect, rtol=1e-5, atol=0)
     assert np.max(np.abs(Li[:, 1:])) < 1e-5 * expect
-    assert expect == pytest.approx(9 * E * kap / 8, rel=0.1)
+    nu = MODELS[model][1]
+    cont = (E / (1 - nu * nu) if model == "stress" else E * (1 - nu) / ((1 + nu) * (1 - 2 * nu))) * kap
+    assert cont == pytest.approx((9 / 8 if model == "stress" else 6 / 5) * E * kap, rel=1e-12)
+    assert expect == pytest.approx(cont, rel=0.1)
 
 
 def test_thickness_scales_only_the_reaction():

@@ -72,7 +72,8 @@ class Beam:
     span: float = 150.0 * MM
     notch_depth: float = 5.0 * MM
     pad_width: float = 5.0 * MM
-    plane: bool = False             # plane stress: one node through the thickness
+    plane: bool = False             # plane body: one node through the thickness
+    plane_strain: bool = False      # with plane: plane strain instead of plane stress
 
     @staticmethod
     def similar(depth: float) -> "Beam":
