@@ -49,6 +49,28 @@ def test_adjoint_matches_oracle_level0(B, law, precision):
         assert e0 < tol and ec < tol
 
 
+@pytest.mark.parametrize("strain", [False, True])
+def test_adjoint_on_the_plane_specimen_matches_oracle(B, strain):
+    """Plane-stress and plane-strain Specimen 3 at level 1 (1,400 nodes):
+    cracking run to its peak, random s0 and c fields, FP64, checkpoint every
+    128 steps."""
+    import dataclasses
+    lv = W.level2d(1)
+    lv = dataclasses.replace(lv, beam=dataclasses.replace(lv.beam, plane_strain=strain))
+    rng = np.random.default_rng(21)
+    M = int(np.prod(lv.shape))
+    s0 = W.S0_MEAN * np.exp(0.1 * rng.standard_normal(M))
+    prob = S.beam_problem(lv, s0=s0)
+    c = prob.c * np.exp(0.05 * rng.standard_normal(M))
+    prob.c = c
+    ref = prob.adjoint()
+    out = B.qoi_grad(B.Mesh.for_level(lv), B.make_params(lv, precision="f64", checkpoint_every=128), s0, c)
+    assert out["Q"] == pytest.approx(ref["Q"], rel=1e-9) and out["nstar"] == ref["nstar"]
+    e0, ec = rel_l2(out["dQ_ds0"], ref["dQ_ds0"]), rel_l2(out["dQ_dc"], ref["dQ_dc"])
+    print(f"plane ({'strain' if strain else 'stress'}) rel L2: ds0 {e0:.2e}, dc {ec:.2e}")
+    assert e0 < 1e-6 and ec < 1e-6
+
+
 def test_adjoint_elastic_limit_stretch_gradient_is_zero(B):
     lv = W.level(0)
     mesh = B.Mesh.for_level(lv)
