@@ -235,6 +235,36 @@ def plane_adaptive_leg(eps=50.0, n_warm=100):
             "mlmc_samples_per_s": sum(out["N"]) / out["wall_s"]}
 
 
+def cost_curve_leg(eps_list=(100.0, 50.0, 25.0), n_warm=100):
+    """Cost of the adaptive estimator against the RMSE target on the
+    plane-stress Specimen 3 (paper's material model, five levels), in bond
+    updates and seconds, beside the cost standard MC would need at the same
+    sampling tolerance: N = V[Q] / eps_s^2 finest-level solves (Eq.
+    MC_num_samples), with V[Q] taken as the level-0 variance.  The slopes
+    are least-squares fits of log cost against log eps."""
+    import numpy as np
+    import workloads as W
+    from paper_2212_04415_amd import mlmc
+    levels = [W.level2d(l) for l in range(5)]
+    run, costs, dofs = mlmc.solver_sampler(levels, seed=6, precision="f32", corr_len=20e-3, n_modes=W.FIELD_MODES,
+                                           mean=W.S0_MEAN, cov=W.FIELD_COV, kl_coefficients=W.kl_coefficients,
+                                           field_model="paper")
+    fine_cost = costs[-1] - costs[-2]          # one finest-level solve alone
+    rows = []
+    for eps in eps_list:
+        out = mlmc.adaptive(run, eps, costs, dofs, n_warm=n_warm, alpha=None, alpha_default=0.5, refinement=4.0)
+        v0 = out["levels"][0][1]
+        n_mc = v0 / out["eps_s"] ** 2
+        rows.append({"eps_N": eps, "levels_used": out["L"] + 1, "converged": out["converged"], "N": out["N"],
+                     "mlmc_bond_updates": out["cost"], "mlmc_wall_s": out["wall_s"],
+                     "mc_solves": n_mc, "mc_bond_updates": n_mc * fine_cost,
+                     "estimate_N": out["estimate"], "bias_estimate_N": out["bias"]})
+    le = np.log([r["eps_N"] for r in rows])
+    slope = lambda key: float(np.polyfit(le, np.log([r[key] for r in rows]), 1)[0])
+    return {"rows": rows, "mlmc_cost_exponent": slope("mlmc_bond_updates"),
+            "mc_cost_exponent": slope("mc_bond_updates")}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +285,8 @@ def main():
                     help="also run the plane-stress Specimen-3 MLMC hierarchy (five levels, paper material model)")
     ap.add_argument("--plane-adaptive", action="store_true",
                     help="also run the adaptive MLMC algorithm on the plane-stress Specimen 3 (RMSE target 50 N)")
+    ap.add_argument("--cost-curve", action="store_true",
+                    help="also run the adaptive MLMC on the plane-stress Specimen 3 at eps = 100 / 50 / 25 N")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="profiling only: time steps per batch solve (default: the workload's 8000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -389,6 +421,8 @@ def main():
         line["plane_stress_mlmc"] = plane_leg()
     if args.plane_adaptive:
         line["plane_stress_mlmc_adaptive"] = plane_adaptive_leg()
+    if args.cost_curve:
+        line["plane_stress_cost_curve"] = cost_curve_leg()
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
