@@ -1,0 +1,67 @@
+"""Degenerate and ragged cases of the time loop on the GPU against the
+oracle: no time step at all, step counts that are not a multiple of the
+captured chunk (1, 63, 65, 130), and a batch of single samples on two levels
+whose step counts do not fill the batch graph's hyper-period."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import solver as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2212_04415_amd import beam as B
+    return torch, B
+
+
+def test_no_time_step_gives_no_peak(env):
+    """With zero steps there is no reaction: the peak is -inf at step 0 on
+    both sides (the maximum over an empty set)."""
+    torch, B = env
+    lv = dataclasses.replace(W.level(0), n_steps=0)
+    ref = S.beam_problem(lv).run(want_state=False)
+    assert ref["Q"] == -np.inf and ref["nstar"] == 0
+    mesh = B.Mesh.for_level(lv)
+    out = B.run(mesh, B.make_params(lv, precision="f64"))
+    assert out["Q"] == -np.inf and out["nstar"] == 0
+    (Q, ns, st), = B.run_batch([B.BatchItem(mesh, B.make_params(lv), 3)])
+    assert torch.all(st == 0) and torch.all(torch.isneginf(Q)) and torch.all(ns == 0)
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 130])
+def test_ragged_step_counts_match_the_oracle(env, n):
+    """Cracking-rate loading (fast enough that the reaction is non-zero from
+    the first steps) for n steps: the FP64 reaction history, peak and step."""
+    torch, B = env
+    lv = dataclasses.replace(W.level(0, fracture=True), n_steps=n, du=2e-7)
+    ref = S.beam_problem(lv).run(want_state=False)
+    out = B.run(B.Mesh.for_level(lv), B.make_params(lv, precision="f64", record_history=True))
+    assert np.allclose(out["R"], ref["R"], rtol=1e-9, atol=1e-9 * np.max(np.abs(ref["R"])))
+    assert out["Q"] == pytest.approx(ref["Q"], rel=1e-9) and out["nstar"] == ref["nstar"]
+
+
+def test_uneven_batch_of_single_samples(env):
+    """One sample on level 0 (37 steps) and one on level 1 (23 steps, half
+    the time step) in one batch: each equals its own single run bit for bit,
+    although neither step count fills the batch graph's replay period."""
+    torch, B = env
+    l0 = dataclasses.replace(W.level(0, fracture=True), n_steps=37, du=2e-7)
+    l1 = dataclasses.replace(W.level(1, fracture=True), n_steps=23, du=1e-7)
+    m0, m1 = B.Mesh.for_level(l0), B.Mesh.for_level(l1)
+    p0, p1 = B.make_params(l0), B.make_params(l1)
+    outs = B.run_batch([B.BatchItem(m0, p0, 1), B.BatchItem(m1, p1, 1)])
+    for mesh, p, (Q, ns, st) in ((m0, p0, outs[0]), (m1, p1, outs[1])):
+        assert int(st[0]) == 0
+        single = B.run(mesh, p)
+        assert Q[0].item() == single["Q"] and ns[0].item() == single["nstar"]
+    for lv, (Q, ns, st) in ((l0, outs[0]), (l1, outs[1])):
+        ref = S.beam_problem(lv).run(want_state=False)
+        assert Q[0].item() == pytest.approx(ref["Q"], rel=5e-3)
