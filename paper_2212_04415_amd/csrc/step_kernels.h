@@ -478,9 +478,9 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         }
         // wa (v + ea) + wb (-v + eb) = (wa - wb) v + wa ea + wb eb: the large
         // symmetric parts cancel exactly before they are scaled.  Pair sums
-        // are chained into the group's partial sum, and each group of four
-        // pairs (eight bonds) enters the compensated accumulator once.
-        constexpr int G = 4;
+        // are chained into the group's partial sum, and each group of eight
+        // pairs (sixteen bonds) enters the compensated accumulator once.
+        constexpr int G = 8;
         constexpr bool first = (I % G == 0);
         const T dw = wa - wb;
         auto part = [&](auto cc, T ea, T eb, T pend) {
