@@ -634,46 +634,72 @@ __device__ __forceinline__ int pop_slot(uint32_t (&m)[4])
 // stretch, damage history and damage law.  A bond's largest stretch is kept in
 // hist once it passes the bond's limit stretch (never decreasing, so damage
 // never heals); `was` says the bond had passed it before (its bit in the
-// node's damage mask), and *now is set when it passes it for the first time.
-// Returns false for a ghost neighbour, which contributes nothing.
+// node's damage mask), and now is set when it passes it for the first time or
+// its history grows.  The pass is bound by the latency of these reads, so they
+// are split from the arithmetic: exc_fetch issues every read of a bond (ghost
+// cells of the padded fields are valid addresses) and exc_finish uses them,
+// letting a lane keep the reads of two bonds in flight.
+template <typename T>
+struct ExcFetch {
+    typename Vec4<T>::t uj;
+    T s0j, gj, cj, kap;
+    int x, y, z, len2;
+};
+
 template <typename T, bool HAS_C, typename Src>
-__device__ __forceinline__ bool exc_bond(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
-                                         const T *__restrict__ S0, T *__restrict__ Hs, const T *__restrict__ Gp,
-                                         int gstep, uint32_t lb1, uint32_t lbh, const typename Vec4<T>::t &ui, T s0i,
-                                         T ci, T gi, int k, bool was, bool &now, T &fx, T &fy, T &fz)
+__device__ __forceinline__ ExcFetch<T> exc_fetch(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
+                                                 const T *__restrict__ S0, const T *__restrict__ Hs,
+                                                 const T *__restrict__ Gp, int gstep, uint32_t lb1, uint32_t lbh,
+                                                 int k, bool was)
 {
-    using V4 = typename Vec4<T>::t;
+    ExcFetch<T> f;
     const uint32_t e = tab.slot[k];
-    const int x = (int)(e & 15u) - 3, y = (int)((e >> 4) & 15u) - 3, z = (int)((e >> 8) & 15u) - 3;
-    const int len2 = (int)(e >> 12);
-    const V4 uj = src.get(x, y, z);
+    f.x = (int)(e & 15u) - 3;
+    f.y = (int)((e >> 4) & 15u) - 3;
+    f.z = (int)((e >> 8) & 15u) - 3;
+    f.len2 = (int)(e >> 12);
+    const int64_t off = (int64_t)f.x + (int64_t)f.y * a.PX + (int64_t)f.z * a.PXY;
+    f.uj = src.get(f.x, f.y, f.z);
+    f.s0j = ld(S0, off, lb1);
+    f.gj = ld(Gp, off * gstep, lb1 * (uint32_t)gstep);
+    f.cj = T(1);
+    if constexpr (HAS_C) f.cj = src.getc(f.x, f.y, f.z);
+    const T *H = (const T *)((const char *)(Hs + (int64_t)k * a.M) + lbh);
+    f.kap = was ? *H : T(0);
+    return f;
+}
+
+// Returns false for a ghost neighbour, which contributes nothing.
+template <typename T, bool HAS_C>
+__device__ __forceinline__ bool exc_finish(const StepParams<T> &a, const SlotLds<T> &tab, T *__restrict__ Hs,
+                                           uint32_t lbh, const typename Vec4<T>::t &ui, T s0i, T ci, T gi, int k,
+                                           const ExcFetch<T> &f, bool &now, T &fx, T &fy, T &fz)
+{
     now = false;
-    if (uj.w == T(0)) return false;
-    const int64_t off = (int64_t)x + (int64_t)y * a.PX + (int64_t)z * a.PXY;
+    if (f.uj.w == T(0)) return false;
     T ex, ey, ez, ry;
-    const T num = num_rt<T>(ui, uj, x, y, z, ex, ey, ez);
-    const T s = stretch_from_num(num, T(len2), tab.len[len2], ry);
-    const T s0b = T(0.5) * (s0i + ld(S0, off, lb1));
-    T *H = (T *)((char *)(Hs + (int64_t)k * a.M) + lbh);
-    T kap = was ? *H : T(0);
+    const T num = num_rt<T>(ui, f.uj, f.x, f.y, f.z, ex, ey, ez);
+    const T s = stretch_from_num(num, T(f.len2), tab.len[f.len2], ry);
+    const T s0b = T(0.5) * (s0i + f.s0j);
+    T kap = f.kap;
     if (s > kap && s > s0b) {
         kap = s;
-        *H = s;
+        *(T *)((char *)(Hs + (int64_t)k * a.M) + lbh) = s;
         now = true;
     }
     T cb = T(1);
-    if constexpr (HAS_C) cb = T(0.5) * (ci + src.getc(x, y, z));
+    if constexpr (HAS_C) cb = T(0.5) * (ci + f.cj);
     T keep = T(1);
     if (kap > s0b) {
         // bond fracture energy: endpoint mean, as for s0 and c
-        const T gb = T(0.5) * (gi + ld(Gp, off * gstep, lb1 * (uint32_t)gstep));
+        const T gb = T(0.5) * (gi + f.gj);
         const T sc = s0b + quot(a.gamma_rel * gb, cb * s0b);
         keep = keep_fraction(a, kap, s0b, sc);
     }
     const T w = keep * s * ry * cb;
-    fx = w * (T(x) + ex);
-    fy = w * (T(y) + ey);
-    fz = w * (T(z) + ez);
+    fx = w * (T(f.x) + ex);
+    fy = w * (T(f.y) + ey);
+    fz = w * (T(f.z) + ez);
     return true;
 }
 
@@ -683,11 +709,12 @@ __device__ __forceinline__ bool exc_bond(const StepParams<T> &a, const Src &src,
 // over its own bonds would take as many rounds as the busiest lane, with most
 // lanes idle.  Instead, round r takes the r-th bond (in slot order) of every
 // node that has more than r, consecutive rounds are packed into a list of up
-// to 64 bonds, and the list is evaluated one bond per lane with the owning
-// node's values fetched across lanes.  Each owner then adds its results round
-// by round, i.e. in slot order, so a node's force is bit-identical to a walk
-// over its own bonds.  Called by every lane of the wave (lanes without a node
-// pass todo = 0); list is this wave's 64-entry slice of block-shared memory.
+// to 128 bonds, and the list is evaluated two bonds per lane (their reads in
+// flight together) with the owning node's values fetched across lanes.  Each
+// owner then adds its results round by round, i.e. in slot order, so a
+// node's force is bit-identical to a walk over its own bonds.  Called by
+// every lane of the wave (lanes without a node pass todo = 0); list is this
+// wave's 128-entry slice of block-shared memory.
 template <typename T, bool KAHAN, bool HAS_C, typename Src>
 __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
                                          const T *__restrict__ S0, T *__restrict__ Hs, const T *__restrict__ Gp,
@@ -696,6 +723,7 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
                                          Acc3<T, KAHAN> &acc, uint16_t *list)
 {
     using V4 = typename Vec4<T>::t;
+    constexpr uint32_t kList = 128;
     const uint32_t lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t cnt = __builtin_popcount(todo[0]) + __builtin_popcount(todo[1]) + __builtin_popcount(todo[2]) +
@@ -711,7 +739,7 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
         for (;;) {
             const uint64_t m = __ballot(cnt > r);
             const uint32_t n = (uint32_t)__popcll(m);
-            if (n == 0 || fill + n > 64u) break;
+            if (n == 0 || fill + n > kList) break;
             if (cnt > r) {
                 const int k = pop_slot(rem);
                 const uint32_t at = fill + (uint32_t)__popcll(m & below);
@@ -723,37 +751,56 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // one listed bond per lane
-        const bool has = lane < fill;
-        const uint32_t ent = has ? list[lane] : (lane << 8);
-        const uint32_t o = ent >> 8;
-        V4 oui;
-        oui.x = shfl_t(ui.x, o);
-        oui.y = shfl_t(ui.y, o);
-        oui.z = shfl_t(ui.z, o);
-        oui.w = T(1);
-        const T os0 = shfl_t(s0i, o);
-        const T oci = HAS_C ? shfl_t(ci, o) : T(1);
-        const T ogi = shfl_t(gi, o);
-        const uint32_t op = shfl_u32(p, o), onode = shfl_u32(node, o), okey = shfl_u32(key, o);
-        T fx = T(0), fy = T(0), fz = T(0);
-        bool now = false, live = false;
-        if (has)
-            live = exc_bond<T, HAS_C>(a, src.rebased(okey), tab, S0, Hs, Gp, gstep, op * (uint32_t)sizeof(T),
-                                      onode * (uint32_t)sizeof(T), oui, os0, oci, ogi, (int)(ent & 127u),
-                                      (ent & 128u) != 0u, now, fx, fy, fz);
-        const uint32_t flags = (live ? 1u : 0u) | (now ? 2u : 0u);
+        // listed bonds lane and lane + 64
+        const bool has0 = lane < fill, has1 = lane + 64u < fill;
+        const uint32_t ent0 = has0 ? list[lane] : (lane << 8), ent1 = has1 ? list[lane + 64u] : (lane << 8);
+        const uint32_t o0 = ent0 >> 8, o1 = ent1 >> 8;
+        V4 u0, u1;
+        u0.x = shfl_t(ui.x, o0);
+        u0.y = shfl_t(ui.y, o0);
+        u0.z = shfl_t(ui.z, o0);
+        u0.w = T(1);
+        u1.x = shfl_t(ui.x, o1);
+        u1.y = shfl_t(ui.y, o1);
+        u1.z = shfl_t(ui.z, o1);
+        u1.w = T(1);
+        const T s00 = shfl_t(s0i, o0), s01 = shfl_t(s0i, o1);
+        const T c00 = HAS_C ? shfl_t(ci, o0) : T(1), c01 = HAS_C ? shfl_t(ci, o1) : T(1);
+        const T g00 = shfl_t(gi, o0), g01 = shfl_t(gi, o1);
+        const uint32_t p0 = shfl_u32(p, o0), p1 = shfl_u32(p, o1);
+        const uint32_t n0 = shfl_u32(node, o0), n1 = shfl_u32(node, o1);
+        const uint32_t k0 = shfl_u32(key, o0), k1 = shfl_u32(key, o1);
+        const uint32_t lh0 = n0 * (uint32_t)sizeof(T), lh1 = n1 * (uint32_t)sizeof(T);
+        ExcFetch<T> f0, f1;
+        if (has0)
+            f0 = exc_fetch<T, HAS_C>(a, src.rebased(k0), tab, S0, Hs, Gp, gstep, p0 * (uint32_t)sizeof(T), lh0,
+                                     (int)(ent0 & 127u), (ent0 & 128u) != 0u);
+        if (has1)
+            f1 = exc_fetch<T, HAS_C>(a, src.rebased(k1), tab, S0, Hs, Gp, gstep, p1 * (uint32_t)sizeof(T), lh1,
+                                     (int)(ent1 & 127u), (ent1 & 128u) != 0u);
+        T fx0 = T(0), fy0 = T(0), fz0 = T(0), fx1 = T(0), fy1 = T(0), fz1 = T(0);
+        bool now0 = false, live0 = false, now1 = false, live1 = false;
+        if (has0)
+            live0 = exc_finish<T, HAS_C>(a, tab, Hs, lh0, u0, s00, c00, g00, (int)(ent0 & 127u), f0, now0, fx0, fy0,
+                                         fz0);
+        if (has1)
+            live1 = exc_finish<T, HAS_C>(a, tab, Hs, lh1, u1, s01, c01, g01, (int)(ent1 & 127u), f1, now1, fx1, fy1,
+                                         fz1);
+        const uint32_t flags = (live0 ? 1u : 0u) | (now0 ? 2u : 0u) | (live1 ? 4u : 0u) | (now1 ? 8u : 0u);
         // owners add their results round by round
         uint32_t base = 0;
         for (uint32_t rr = r0; rr < r; ++rr) {
             const uint64_t m = __ballot(cnt > rr);
             const bool mi = cnt > rr;
-            const uint32_t srcl = mi ? base + (uint32_t)__popcll(m & below) : lane;
-            const T vx = shfl_t(fx, srcl), vy = shfl_t(fy, srcl), vz = shfl_t(fz, srcl);
-            const uint32_t fl = shfl_u32(flags, srcl);
+            const uint32_t idx = mi ? base + (uint32_t)__popcll(m & below) : lane;
+            const uint32_t srcl = idx & 63u;
+            const bool hi = idx >= 64u;
+            const T ax = shfl_t(fx0, srcl), ay = shfl_t(fy0, srcl), az = shfl_t(fz0, srcl);
+            const T bx = shfl_t(fx1, srcl), by = shfl_t(fy1, srcl), bz = shfl_t(fz1, srcl);
+            const uint32_t fl = shfl_u32(flags, srcl) >> (hi ? 2 : 0);
             if (mi) {
                 const int k = pop_slot(walk);
-                if (fl & 1u) acc.add(vx, vy, vz);
+                if (fl & 1u) acc.add(hi ? bx : ax, hi ? by : ay, hi ? bz : az);
                 if (fl & 2u) set_mask_bit(dm, k);
             }
             base += (uint32_t)__popcll(m);
@@ -944,9 +991,9 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
     __shared__ T ctile[(LDS && HAS_C) ? BR::TILE : 1];
     __shared__ SlotLds<T> tab;
     // the previous reaction's partial sums, then each wave's exception list
-    __shared__ double scratch[64];
-    static_assert(BR::N <= 256, "one 64-entry exception list per wave in 512 bytes");
-    uint16_t *list = (uint16_t *)scratch + 64 * (threadIdx.x / 64);
+    __shared__ double scratch[128];
+    static_assert(BR::N <= 256, "one 128-entry exception list per wave in 1 KB");
+    uint16_t *list = (uint16_t *)scratch + 128 * (threadIdx.x / 64);
     const int64_t per_xcd = gridDim.x / kXcds;
     const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
     if (item >= a.n_items) return;
