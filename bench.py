@@ -409,23 +409,29 @@ def main():
                                     "peak_cov": float(qf.std() / qf.mean()),
                                     "load_per_step_mm": lvf.du * 1e3}
 
+    def leg(key, fn, *fargs, **fkw):
+        t = time.perf_counter()
+        line[key] = fn(*fargs, **fkw)
+        print(f"[bench] {key} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+
+    print("[bench] headline done", file=sys.stderr, flush=True)
     if args.mlmc:
-        line["mlmc_hierarchy"] = mlmc_leg(fracture=True)
+        leg("mlmc_hierarchy", mlmc_leg, fracture=True)
     if args.mlmc_paper:
-        line["mlmc_hierarchy_paper_material"] = mlmc_leg(fracture=True, field_model="paper")
+        leg("mlmc_hierarchy_paper_material", mlmc_leg, fracture=True, field_model="paper")
     if args.adaptive:
-        line["mlmc_adaptive"] = adaptive_leg()
+        leg("mlmc_adaptive", adaptive_leg)
     if args.sweep:
-        line["size_sweep"] = sweep_leg()
+        leg("size_sweep", sweep_leg)
     if args.plane:
-        line["plane_stress_mlmc"] = plane_leg()
+        leg("plane_stress_mlmc", plane_leg)
     if args.plane_adaptive:
-        line["plane_stress_mlmc_adaptive"] = plane_adaptive_leg()
+        leg("plane_stress_mlmc_adaptive", plane_adaptive_leg)
     if args.cost_curve:
-        line["plane_stress_cost_curve"] = cost_curve_leg()
+        leg("plane_stress_cost_curve", cost_curve_leg)
 
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        leg("cpu_baseline", cpu_baseline)
 
     print(json.dumps(line), flush=True)
 
