@@ -1,0 +1,38 @@
+"""CPU checks of the benchmark driver's contract: more than one GPU is refused
+with a message, and the roofline helpers read the committed profiles only
+when they were taken on the current kernel source."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_profile_traffic_matches_the_current_kernel_source():
+    """The committed counter summary names the benchmarked kernel and its
+    source hash; traffic is reported for that kernel and withheld for any
+    other."""
+    with open(os.path.join(ROOT, "profiles", "step_kernel_L1x64_pmc.json")) as fh:
+        d = json.load(fh)
+    kernel = d["kernel"].removeprefix("pdmi::")
+    assert kernel in bench.SHAPE_KERNELS
+    if d["kernel_source_hash"] == bench.kernel_source_hash():
+        t = bench.traffic_from_profiles(kernel)
+        assert t == d["hbm_bytes_per_launch"] and t > 0
+    other = [k for k in bench.SHAPE_KERNELS if k != kernel][0]
+    assert bench.traffic_from_profiles(other) is None
+
+
+def test_peak_is_the_vector_fp32_rate():
+    assert abs(bench.PEAK_TFLOPS_F32 - 157.2864) < 1e-9
