@@ -177,19 +177,20 @@ def sweep_leg(steps=1000):
     return out
 
 
-def plane_leg(samples=(2152, 567, 204, 67, 18)):
+def plane_leg(samples=(2152, 567, 204, 67, 18), notched=True, eps_s=10.0):
     """The paper's own case: the plane-stress Specimen 3 (350 x 100 mm,
     t = 50 mm, half-notched) on the five levels of its Table discretisation
     (350 ... 89,600 nodes), the paper's material model (exponential
     covariance on the plane, Weibull strength, fib relations), every level-l
     sample paired with a coarse solve on the same coefficients, one batched
     FP32 call.  The sample counts are the paper's allocation for this
-    specimen at a sampling tolerance of 10 N (section 6.2)."""
+    specimen at a sampling tolerance of 10 N (section 6.2).  notched=False:
+    the unnotched specimen of case study 2 (section 6.3)."""
     import numpy as np
     import torch
     import workloads as W
     from paper_2212_04415_amd import mlmc
-    levels = [W.level2d(l) for l in range(len(samples))]
+    levels = [W.level2d(l, notched=notched) for l in range(len(samples))]
     out = mlmc.coupled_batch(levels, list(samples), seed=5, precision="f32", corr_len=20e-3,
                              n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
                              kl_coefficients=W.kl_coefficients, field_model="paper")
@@ -202,11 +203,11 @@ def plane_leg(samples=(2152, 567, 204, 67, 18)):
     quant = mlmc.cdf(fine, coarse, u)
     # standard Monte Carlo at the same sampling tolerance (Eq. MC_num_samples):
     # N = V[Q_L] / eps_s^2 solves of the finest level, V from its fine samples
-    eps_s = 10.0
     qL = np.asarray(out["Q"][L - 1][:samples[L - 1]])
     n_mc = float(np.var(qL, ddof=1)) / eps_s ** 2
     mc_cost = n_mc * out["bonds"][L - 1] * out["steps"][L - 1]
-    return {"workload": "specimen3_plane_stress_paper_material", "nodes": out["nodes"], "bonds": out["bonds"],
+    return {"workload": "specimen3_plane_stress_paper_material" + ("" if notched else "_unnotched"),
+            "nodes": out["nodes"], "bonds": out["bonds"], "solves_per_level_fine": list(samples),
             "mc_equivalent": {"eps_s_N": eps_s, "N": n_mc, "bond_updates": mc_cost,
                               "mlmc_bond_updates": bu, "cost_ratio_mc_over_mlmc": mc_cost / bu},
             "steps": out["steps"], "solves_per_level": out["solves"], "wall_s": out["wall_s"],
@@ -284,6 +285,9 @@ def main():
                     help="also time the size-sweep beams (D = 50..400 mm, 32 samples, first 1000 steps)")
     ap.add_argument("--plane", action="store_true",
                     help="also run the plane-stress Specimen-3 MLMC hierarchy (five levels, paper material model)")
+    ap.add_argument("--plane-unnotched", action="store_true",
+                    help="also run the unnotched Specimen-3 hierarchy (case study 2) with the paper's allocation at a "
+                         "50 N sampling tolerance (1624/479/230/63/22 samples)")
     ap.add_argument("--plane-adaptive", action="store_true",
                     help="also run the adaptive MLMC algorithm on the plane-stress Specimen 3 (RMSE target 50 N)")
     ap.add_argument("--cost-curve", action="store_true",
@@ -427,6 +431,8 @@ def main():
         leg("size_sweep", sweep_leg)
     if args.plane:
         leg("plane_stress_mlmc", plane_leg)
+    if args.plane_unnotched:
+        leg("plane_stress_mlmc_unnotched", plane_leg, samples=(1624, 479, 230, 63, 22), notched=False, eps_s=50.0)
     if args.plane_adaptive:
         leg("plane_stress_mlmc_adaptive", plane_adaptive_leg)
     if args.cost_curve:

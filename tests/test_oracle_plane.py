@@ -218,3 +218,20 @@ def test_plane_beam_cracks_from_the_notch():
     assert np.all(r["kappa"][top] > 10 * S0)
     assert np.all(np.abs(mid[top, 0] - 0.5 * lv.beam.length) < p.delta)
     assert np.all((mid[top, 2] >= lv.beam.notch_depth - 0.5 * lv.dx) & (mid[top, 2] < lv.beam.notch_depth + p.delta))
+
+
+def test_unnotched_specimen_is_mirror_symmetric():
+    """Case study 2's unnotched Specimen 3 (lambda = 0) is symmetric about
+    mid-span in geometry, pads and loading, so the homogeneous solve is too:
+    u_x(L - x) = -u_x(x) and u_z(L - x) = u_z(x), to rounding, through the
+    first cracking steps."""
+    lv = W.level2d(1, notched=False, steps_scale=0.3)
+    p = S.beam_problem(lv)
+    assert p.n_bonds == G.unique_bonds(lv.shape, W.M_RATIO)[0].size      # no bond is cut
+    r = p.run()
+    nx, ny, nz = lv.shape
+    u = r["u"].reshape(nz, nx, 3)
+    scale = np.max(np.abs(u))
+    assert np.max(np.abs(u[:, ::-1, 0] + u[:, :, 0])) < 1e-9 * scale
+    assert np.max(np.abs(u[:, ::-1, 2] - u[:, :, 2])) < 1e-9 * scale
+    assert np.max(r["kappa"]) > S0                                           # damage has started

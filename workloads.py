@@ -132,11 +132,16 @@ STEPS_2D_L0 = 2000
 DU_2D_L0 = 5.0e-8           # m per step at dx = 10 mm (peak load mid-run)
 
 
-def level2d(ell: int, law: int = LAW_TRILINEAR, steps_scale: float = 1.0) -> Level:
-    """Level ell of the plane-stress Specimen 3: dx = 10 mm / 2^ell with dt,
-    steps and the displacement increment scaled with dx."""
+# The unnotched Specimen 3 of section 6.3 (case study 2, lambda = 0).
+SPECIMEN3_UNNOTCHED = replace(SPECIMEN3, notch_depth=0.0)
+
+
+def level2d(ell: int, law: int = LAW_TRILINEAR, steps_scale: float = 1.0, notched: bool = True) -> Level:
+    """Level ell of the plane-stress Specimen 3 (half-notched, or unnotched
+    with notched=False): dx = 10 mm / 2^ell with dt, steps and the
+    displacement increment scaled with dx."""
     r = 2 ** ell
-    return Level(beam=SPECIMEN3, dx=10.0 * MM / r, dt=DT_2D_L0 / r,
+    return Level(beam=SPECIMEN3 if notched else SPECIMEN3_UNNOTCHED, dx=10.0 * MM / r, dt=DT_2D_L0 / r,
                  n_steps=int(round(STEPS_2D_L0 * r * steps_scale)), du=DU_2D_L0 / r, law=law)
 
 
