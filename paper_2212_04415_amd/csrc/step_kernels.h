@@ -479,8 +479,10 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         // wa (v + ea) + wb (-v + eb) = (wa - wb) v + wa ea + wb eb: the large
         // symmetric parts cancel exactly before they are scaled.  Pair sums
         // are chained into the group's partial sum, and each group of eight
-        // pairs (sixteen bonds) enters the compensated accumulator once.
-        constexpr int G = 8;
+        // pairs (sixteen bonds) enters the compensated accumulator once; the
+        // 14-pair plane loop keeps groups of four, whose shorter chains it
+        // needs to hide their latency.
+        constexpr int G = PLANE ? 4 : 8;
         constexpr bool first = (I % G == 0);
         const T dw = wa - wb;
         auto part = [&](auto cc, T ea, T eb, T pend) {
