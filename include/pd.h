@@ -55,7 +55,9 @@ enum { PD_FIELD_S0 = 0, PD_FIELD_C = 1, PD_FIELD_GF = 2 };
 enum { PD_DTYPE_F32 = 0, PD_DTYPE_F64 = 1 };
 /* Launch shapes of the step kernel: nodes per block as an x-by-y-by-z brick
  * staged with its halo in LDS, or 256 consecutive nodes read through the
- * caches.  All shapes give bit-identical results. */
+ * caches.  On a mesh one node thick (a plane body) the three brick shapes
+ * are 64x4, 32x8 and 32x4 patches of the x-z plane.  All shapes give
+ * bit-identical results. */
 enum {
     PD_SHAPE_AUTO = -1,
     PD_SHAPE_LDS_16x4x4 = 0,
@@ -188,16 +190,18 @@ PD_API int pd_run_state(pd_run_h r, double *u_out, double *kappa_out);
 
 PD_API int pd_free_run(pd_run_h r);
 
-/* A batch of independent samples over one or more meshes (levels), run as
- * one launch per time tick over every active (sample, node tile) work item,
- * replayed from a captured HIP graph.  Items whose dt is an integer multiple
- * of the finest dt step on the matching ticks.  Per item: s0 (device,
+/* A batch of independent samples over one or more meshes (levels): each
+ * item steps all its samples with one launch per time step, and the items
+ * run as parallel branches of a captured HIP graph that is replayed.  Items
+ * whose dt is an integer multiple of the finest dt step on the matching
+ * ticks (ratios up to an lcm of 4096).  Per item: s0 (device,
  * [n_samples][n_nodes], dtype = field_dtype, NULL = homogeneous p->s0),
  * c (micromodulus, device or NULL), gf (fracture energy in N/m, device or
  * NULL = homogeneous p->GF); outputs qoi (device FP64 [n_samples]), nstar (device
  * int64 [n_samples], nullable), status (device int32 [n_samples], nullable;
- * PD_OK or PD_ENONFINITE).  Async on stream; the caller's buffers must stay
- * valid until it completes.  All items share precision and accumulate. */
+ * PD_OK or PD_ENONFINITE).  Enqueued on stream and synchronised before it
+ * returns (the library's work buffers are released).  All items share
+ * precision and accumulate. */
 typedef struct {
     pd_mesh mesh;
     const pd_params *params;
