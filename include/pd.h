@@ -233,8 +233,8 @@ PD_API int pd_autotune(pd_mesh m, const pd_params *p, int64_t n_samples, void *s
 
 /* Pins the launch shape of every later run on this mesh (PD_SHAPE_AUTO
  * restores tuning).  Shapes a configuration cannot use fall back to one it
- * can (FP64: PD_SHAPE_GLOBAL_256; PD_ACC_PLAIN or a micromodulus field: the
- * 16x4x4 brick or the global shape).  Fails with PD_EINVAL for an unknown
+ * can (FP64: PD_SHAPE_GLOBAL_256; PD_ACC_PLAIN: the 16x4x4 brick or the
+ * global shape).  Fails with PD_EINVAL for an unknown
  * shape. */
 PD_API int pd_set_launch_shape(pd_mesh m, int32_t shape);
 

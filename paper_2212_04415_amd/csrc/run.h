@@ -207,12 +207,13 @@ struct Solve {
 };
 
 // The shape a solve can actually launch with: FP64 has the global shape
-// only; uncompensated accumulation (an ablation) and micromodulus fields
-// have the default brick and the global shape.
+// only; uncompensated accumulation (an ablation) has the default brick and
+// the global shape.
 static int effective_shape(bool f64, bool kahan, bool has_c, int shape)
 {
+    (void)has_c;
     if (f64) return PD_SHAPE_GLOBAL_256;
-    if ((!kahan || has_c) && shape != PD_SHAPE_GLOBAL_256) return PD_SHAPE_LDS_16x4x4;
+    if (!kahan && shape != PD_SHAPE_GLOBAL_256) return PD_SHAPE_LDS_16x4x4;
     return shape;
 }
 

@@ -16,7 +16,7 @@ template <typename T, bool KAHAN, bool HAS_C>
 static void launch_shape(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<T> &a)
 {
     if (plane) {
-        if constexpr (sizeof(T) == 4 && KAHAN && !HAS_C) {
+        if constexpr (sizeof(T) == 4 && KAHAN) {
             switch (shape) {
             case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<64, 4>><<<grid, 256, 0, st>>>(a); return;
             case PD_SHAPE_LDS_8x8x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<32, 8>><<<grid, 256, 0, st>>>(a); return;
@@ -32,7 +32,7 @@ static void launch_shape(int shape, bool plane, dim3 grid, hipStream_t st, const
         step_kernel<T, KAHAN, HAS_C, false, PlaneBrick<256, 1>><<<grid, 256, 0, st>>>(a);
         return;
     }
-    if constexpr (sizeof(T) == 4 && KAHAN && !HAS_C) {
+    if constexpr (sizeof(T) == 4 && KAHAN) {
         switch (shape) {
         case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4, 2>><<<grid, 256, 0, st>>>(a); return;
         case PD_SHAPE_LDS_8x8x4: step_kernel<T, KAHAN, HAS_C, true, Brick<8, 8, 4>><<<grid, 256, 0, st>>>(a); return;

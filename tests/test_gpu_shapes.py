@@ -94,8 +94,25 @@ def test_autotune_reports_every_usable_shape(B, pd):
 
 
 def test_unusable_pinned_shape_falls_back(B, pd, torch):
-    """A micromodulus field has the default brick and the global shape only;
-    pinning another shape runs the default brick, with identical results."""
+    """Uncompensated accumulation (the ablation) has the default brick and the
+    global shape only; pinning another shape runs the default brick, with
+    identical results."""
+    lv = W.level(0, fracture=True, steps_scale=0.25)
+    mesh = B.Mesh.for_level(lv)
+    S = 3
+    s0 = torch.tensor(fields(mesh.n_nodes, S, 7), device="cuda")
+    p = B.make_params(lv, accumulate="plain")
+    outs = []
+    for shape in (pd.PD_SHAPE_LDS_16x4x4, pd.PD_SHAPE_LDS_8x8x4, pd.PD_SHAPE_GLOBAL_256):
+        mesh.set_launch_shape(shape)
+        Q, ns, st = B.run_batch([B.BatchItem(mesh, p, S, s0)])[0]
+        assert torch.all(st == 0)
+        outs.append(Q.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_every_shape_agrees_with_a_micromodulus_field(B, pd, torch):
+    """With per-node s0 and c every launch shape gives the same peaks."""
     lv = W.level(0, fracture=True, steps_scale=0.25)
     mesh = B.Mesh.for_level(lv)
     S = 3
@@ -104,9 +121,10 @@ def test_unusable_pinned_shape_falls_back(B, pd, torch):
     c = torch.tensor(np.exp(0.1 * rng.standard_normal((S, mesh.n_nodes))), device="cuda")
     p = B.make_params(lv)
     outs = []
-    for shape in (pd.PD_SHAPE_LDS_16x4x4, pd.PD_SHAPE_LDS_8x8x4, pd.PD_SHAPE_GLOBAL_256):
+    for shape in range(pd.PD_N_SHAPES):
         mesh.set_launch_shape(shape)
         Q, ns, st = B.run_batch([B.BatchItem(mesh, p, S, s0, c)])[0]
         assert torch.all(st == 0)
-        outs.append(Q.cpu().numpy())
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+        outs.append((Q.cpu().numpy(), ns.cpu().numpy()))
+    for q, n in outs[1:]:
+        assert np.array_equal(q, outs[0][0]) and np.array_equal(n, outs[0][1])
