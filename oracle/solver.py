@@ -4,7 +4,9 @@ TEST INFRASTRUCTURE ONLY (tests, the smoke check and the benchmark's CPU
 baseline).  Nothing in the product library imports this module.
 
 Material constants (appendix A):
-* micromodulus c = 12 E / (pi delta^4) in 3D (Eq. bond_stiffness_constant);
+* micromodulus c = 12 E / (pi delta^4) in 3D, 9 E / (pi t delta^3) in plane
+  stress and 48 E / (5 pi t delta^3) in plane strain
+  (Eq. bond_stiffness_constant), nodal volume dx^3 or dx^2 t;
 * per-bond values from per-node fields are endpoint means,
   c_b = (c_i + c_j)/2 and s0_b = (s0_i + s0_j)/2, so bond forces stay
   equal and opposite;
