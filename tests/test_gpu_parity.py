@@ -256,3 +256,55 @@ def test_batched_fp32_level1_full_size_matches_oracle(B, torch):
     for k, ref in zip(picks, refs):
         assert Q[k].item() == pytest.approx(ref["Q"], rel=5e-3)
         assert abs(ns[k].item() - ref["nstar"]) <= 0.02 * lv.n_steps
+
+
+@pytest.fixture(scope="module")
+def level2_refs():
+    """The level-2 mesh (140 x 40 x 40 nodes, 12.8 M bonds) for 120 steps at
+    1e-6 m per step: the stress wave reaches the supports after ~50 steps and
+    the reaction peaks near step 100 with bonds under the load pad damaged.
+    One homogeneous problem and two lognormal-field samples."""
+    import dataclasses
+    lv = dataclasses.replace(W.level(2, fracture=True), n_steps=120, du=1e-6)
+    ob = OKL.Basis3D((lv.beam.length, lv.beam.thickness, lv.beam.depth), W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    pos = G.node_positions(lv.shape, lv.dx)
+    xi = W.kl_coefficients(2, 2, stream=7)
+    fields = OKL.lognormal_field(ob, pos, xi, W.S0_MEAN, W.FIELD_COV)
+    probs = [S.beam_problem(lv)] + [S.beam_problem(lv, s0=fields[k]) for k in range(2)]
+    refs = oracle_runs(probs, want_state=True)
+    return lv, xi, refs
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_level2_run_matches_oracle(B, level2_refs, precision):
+    lv, _, refs = level2_refs
+    ref = refs[0]
+    assert 0.5 * lv.n_steps < ref["nstar"] < lv.n_steps
+    mesh = B.Mesh.for_level(lv)
+    out = B.run(mesh, B.make_params(lv, precision=precision, record_history=True), want_state=True)
+    assert out["Q"] == pytest.approx(ref["Q"], rel=1e-9 if precision == "f64" else 5e-3)
+    assert abs(out["nstar"] - ref["nstar"]) <= (0 if precision == "f64" else 2)
+    assert rel_l2(out["u"], ref["u"]) < (1e-9 if precision == "f64" else 1e-4)
+    live = np.abs(ref["R"]) > 1e-3 * ref["Q"]
+    assert rel_l2(out["R"][live], ref["R"][live]) < (1e-9 if precision == "f64" else 1e-4)
+    damaged_ref = int(np.sum(ref["kappa"] > W.S0_MEAN))
+    assert damaged_ref > 0
+    assert np.sum(out["kappa"] > W.S0_MEAN) == pytest.approx(2 * damaged_ref, rel=1e-3 if precision == "f64" else 0.05)
+
+
+@pytest.mark.slow
+def test_level2_batch_matches_oracle(B, torch, level2_refs):
+    """Two lognormal-field samples on the level-2 mesh through pd_run_batch
+    in FP32 with compensated accumulation, the launch path of the multilevel
+    batch, against the oracle on the same KL coefficients."""
+    lv, xi, refs = level2_refs
+    mesh = B.Mesh.for_level(lv)
+    kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    s0 = kl.lognormal(torch.tensor(xi), W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
+    (Q, ns, st), = B.run_batch([B.BatchItem(mesh, B.make_params(lv), 2, s0)])
+    assert torch.all(st == 0)
+    for k in range(2):
+        ref = refs[1 + k]
+        assert Q[k].item() == pytest.approx(ref["Q"], rel=5e-3)
+        assert abs(ns[k].item() - ref["nstar"]) <= 2
