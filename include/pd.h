@@ -134,7 +134,10 @@ typedef struct {
 /* Build the lattice and the support / load node sets (host only).
  * Fails with PD_EINVAL if an extent is not a multiple of dx, the notch
  * position or depth is not a multiple of dx/2, or a node centre lies on a pad
- * face.  *out receives a new handle. */
+ * face, or if the grid with its three ghost layers per face has more than
+ * 2^27 cells (the step kernels address one sample's arrays with 32-bit byte
+ * offsets: an FP64 displacement cell is 32 bytes).  *out receives a new
+ * handle. */
 PD_API int pd_build_mesh(const pd_mesh_desc *desc, pd_mesh *out);
 
 /* Neighbourhoods |x' - x| <= delta (paper section 2.1, Eq. PD_Horizon) as a

@@ -93,6 +93,9 @@ int build_mesh(const pd_mesh_desc *d, pd_mesh_s *m)
     m->PY = m->ny + 2 * kHalo;
     m->PZ = m->nz + 2 * kHalo;
     m->P = (int64_t)m->PX * m->PY * m->PZ;
+    // the step kernels form per-lane byte offsets of up to 32 bytes per cell in 32 bits
+    if (m->P > (int64_t(1) << 27))
+        return fail(PD_EINVAL, "mesh too large: %lld cells with ghost layers (at most 2^27)", (long long)m->P);
 
     // notch plane x = L/2 is at half-cell coordinate nx; its tip 2a/dx
     m->notch_X = m->nx;

@@ -150,3 +150,20 @@ def test_plane_mesh_rejects_bad_thickness(extent_y, thickness, strain):
     rc, h = build(W.SPECIMEN3, 10e-3, extent_y=extent_y, thickness=thickness, plane_strain=strain)
     assert rc == pd.PD_EINVAL and not h.value
     assert "thick" in pd.pd_last_error() or "plane_strain" in pd.pd_last_error()
+
+
+def test_mesh_size_limit_is_the_kernels_addressing_limit():
+    """A cube of 506 nodes per side has exactly 2^27 cells with its ghost
+    layers and is accepted; one more node per side is refused with a message
+    (the step kernels' per-lane byte offsets are 32-bit)."""
+    dx = 1e-3
+    for n, ok in ((506, True), (507, False)):
+        beam = W.Beam(length=n * dx, thickness=n * dx, depth=n * dx, span=400e-3, notch_depth=100e-3,
+                      pad_width=10e-3)
+        rc, h = build(beam, dx)
+        if ok:
+            assert rc == pd.PD_OK, pd.pd_last_error()
+            pd.lib().pd_free_mesh(h)
+        else:
+            assert rc == pd.PD_EINVAL
+            assert "too large" in pd.pd_last_error()
