@@ -19,7 +19,9 @@ constexpr double kClusterRtol = 1e-8;
 constexpr int kMaxExpNodes = 20000;
 constexpr int kModeChunk = 16;
 
-static unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+// blocks for n elements along x, capped at 2^20 (kernels whose n can pass
+// 2^28, the per-sample maps over several samples, loop with a grid stride)
+static unsigned nblocks(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, int64_t(1) << 20); }
 
 // node-centre positions of a mesh, [M][3]; a plane-stress body's nodes lie
 // on the plane y = 0 whatever the spacing, so every level samples the field
@@ -94,8 +96,7 @@ struct FibConst {
 template <typename O>
 __global__ void fib_kernel(const double *g, int64_t n, FibConst f, O *s0, O *c, O *gf)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     const double q = 0.5 * erfc(g[t] * 0.70710678118654752);     // 1 - Phi(g)
     const double fc = f.lam_w * pow(-log(q), f.inv_m);
     const double E = f.alpha_E * 21.5e9 * cbrt(fc / 10.0e6);
@@ -104,6 +105,7 @@ __global__ void fib_kernel(const double *g, int64_t n, FibConst f, O *s0, O *c, 
     if (s0) s0[t] = (O)(ft / E);
     if (c) c[t] = (O)(f.c_scale * E);
     if (gf) gf[t] = (O)(73.0 * pow(fc / 1.0e6, 0.18));
+    }
 }
 
 // Canonical basis of each cluster (eigenvalues equal to kClusterRtol): the

@@ -25,10 +25,10 @@ __global__ void init_state_kernel(typename Vec4<T>::t *u0, typename Vec4<T>::t *
                                   int nx, int ny, int nz, int PX, int64_t PXY, const NodeInfo *info,
                                   double load0)
 {
-    // one thread per padded cell of every sample; real nodes get flag 1 and
-    // the first prescribed load displacement, ghosts are all zero
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= P * S) return;
+    // every padded cell of every sample (grid-stride); real nodes get flag 1
+    // and the first prescribed load displacement, ghosts are all zero
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < P * S;
+         g += (int64_t)gridDim.x * blockDim.x) {
     int64_t q = g % P;
     int i = (int)(q % PX) - kHalo;
     int64_t rr = q / PX;
@@ -43,6 +43,7 @@ __global__ void init_state_kernel(typename Vec4<T>::t *u0, typename Vec4<T>::t *
     }
     u0[g] = v;
     u1[g] = v;
+    }
 }
 
 template <typename T, typename In>
@@ -50,8 +51,8 @@ __global__ void fields_kernel(T *s0pad, T *cpad, T *gpad, const In *s0, const In
                               double inv_cref, double inv_gref, int64_t P, int64_t M, int64_t S, int nx, int ny,
                               int nz, int PX, int64_t PXY, int64_t s0_stride, int64_t c_stride, int64_t gf_stride)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= P * S) return;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < P * S;
+         g += (int64_t)gridDim.x * blockDim.x) {
     int64_t sample = g / P, q = g % P;
     int i = (int)(q % PX) - kHalo;
     int64_t rr = q / PX;
@@ -67,14 +68,15 @@ __global__ void fields_kernel(T *s0pad, T *cpad, T *gpad, const In *s0, const In
     s0pad[g] = sv;
     if (cpad) cpad[g] = cv;
     if (gpad) gpad[g] = gv;
+    }
 }
 
 template <typename T>
 __global__ void threshold_kernel(T *thr, const T *s0pad, int64_t P, int64_t M, int64_t S, int nx, int ny, int PX,
                                  int64_t PXY)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= M * S) return;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < M * S;
+         g += (int64_t)gridDim.x * blockDim.x) {
     int64_t sample = g / M, node = g % M;
     int ix = (int)(node % nx);
     int64_t r = node / nx;
@@ -88,19 +90,19 @@ __global__ void threshold_kernel(T *thr, const T *s0pad, int64_t P, int64_t M, i
         mn = fmin(mn, fmin(S0[p + off], S0[p - off]));
     }
     thr[g] = T(0.5) * (S0[p] + mn);
+    }
 }
 
 template <typename T>
 __global__ void fill_kernel(T *x, int64_t n, T v)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < n) x[g] = v;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+        x[g] = v;
 }
 
 static __global__ void init_qoi_kernel(double *Q, int64_t *nstar, int32_t *status, int64_t *step, int64_t S)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < S) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < S; g += (int64_t)gridDim.x * blockDim.x) {
         Q[g] = -INFINITY;
         nstar[g] = 0;
         status[g] = PD_OK;
@@ -108,7 +110,16 @@ static __global__ void init_qoi_kernel(double *Q, int64_t *nstar, int32_t *statu
     }
 }
 
-static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+// Blocks for n elements, capped so that a dispatch's work-item count stays
+// far inside its 32-bit range (the history of a large batch alone can hold
+// more than 2^32 values).  Kernels over several samples' arrays loop with a
+// grid stride; the cap (2^28 threads) is above the largest padded grid of one
+// sample, so per-sample and per-node kernels never reach it.
+constexpr int64_t kMaxBlocks = int64_t(1) << 20;
+static unsigned blocks_for(int64_t n, int b = 256)
+{
+    return (unsigned)std::min<int64_t>((n + b - 1) / b, kMaxBlocks);
+}
 
 // ---------------------------------------------------------------- run buffers
 struct RunBuffers {
