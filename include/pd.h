@@ -168,7 +168,8 @@ PD_API int pd_set_material_field(pd_mesh m, int32_t field, int64_t n_samples, co
  * Eq. PD_EOM_Dynamic): L_i = sum_j c_b (1 - d_b) s_ij e_ij V with undamaged
  * bonds (d_b = 0).  u_host: [n_samples][n_nodes][3] displacements (m);
  * L_host: [n_samples][n_nodes][3] force densities (N/m^3).  Host buffers;
- * synchronous.  Uses the sample's s0 / c fields when set. */
+ * synchronous.  Uses the sample's s0 / c fields when set.  n_samples: 1 to
+ * 65535, within the one-launch bound of pd_run_batch. */
 PD_API int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double *u_host,
                   double *L_host, void *stream);
 
@@ -204,7 +205,9 @@ PD_API int pd_free_run(pd_run_h r);
  * int64 [n_samples], nullable), status (device int32 [n_samples], nullable;
  * PD_OK or PD_ENONFINITE).  Enqueued on stream and synchronised before it
  * returns (the library's work buffers are released).  All items share
- * precision and accumulate. */
+ * precision and accumulate.  n_samples per item: 1 to 65535, and at most as
+ * many as one step launch over the mesh's tiles can hold (2^32 - 1
+ * work-items for every launch shape); PD_EINVAL otherwise. */
 typedef struct {
     pd_mesh mesh;
     const pd_params *params;

@@ -148,15 +148,18 @@ struct RunBuffers {
     }
 };
 
+static int check_launch_size(const pd_mesh_s *m, int64_t S);
+
 static int alloc_run(const pd_mesh_s *m, int S, bool f64, bool kahan, bool has_c, bool want_hist_R, int64_t n_steps,
                      RunBuffers &b, bool outputs, bool has_g = false)
 {
+    int rc = check_launch_size(m, S);
+    if (rc) return rc;
     b.S = S;
     b.f64 = f64;
     b.kahan = kahan && !f64;
     b.has_c = has_c;
     size_t ts = f64 ? 8 : 4, v4 = 4 * ts;
-    int rc;
     for (int h = 0; h < 2; ++h)
         if ((rc = b.alloc(&b.u[h], v4 * m->P * S))) return rc;
     if ((rc = b.alloc(&b.vh, v4 * m->M * S))) return rc;
@@ -206,6 +209,23 @@ constexpr LaunchShape kPlaneShapes[PD_N_SHAPES] = {
 // A body one node thick has neighbours in the x-z plane only; its step
 // kernels visit the 28 in-plane offsets.
 static inline bool plane_mesh(const pd_mesh_s *m) { return m->ny == 1; }
+
+// A step launch covers every (sample, tile) work item with one block; the
+// dispatch counts its work-items in 32 bits, so every shape the solve might
+// take (the autotuner tries them all) must stay below 2^32 work-items.
+static int check_launch_size(const pd_mesh_s *m, int64_t S)
+{
+    for (const LaunchShape &sh : plane_mesh(m) ? kPlaneShapes : kShapes) {
+        const int64_t tiles = sh.lds ? (int64_t)((m->nx + sh.bx - 1) / sh.bx) * ((m->ny + sh.by - 1) / sh.by) *
+                                           ((m->nz + sh.bz - 1) / sh.bz)
+                                     : (m->M + sh.threads - 1) / sh.threads;
+        const int64_t blocks = (tiles * S + kXcds - 1) / kXcds * kXcds;
+        if (blocks * sh.threads > (int64_t)UINT32_MAX)
+            return fail(PD_EINVAL, "%lld samples of this mesh exceed one launch (%lld work-items; at most 2^32 - 1)",
+                        (long long)S, (long long)(blocks * sh.threads));
+    }
+    return PD_OK;
+}
 
 // Common state of one (mesh, params, samples) solve.
 struct Solve {

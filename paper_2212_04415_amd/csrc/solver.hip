@@ -174,7 +174,7 @@ int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double
                   void *stream)
 {
     if (!m || !p || !u_host || !L_host) return fail(PD_EINVAL, "null argument");
-    if (n_samples < 1) return fail(PD_EINVAL, "n_samples must be positive");
+    if (n_samples < 1 || n_samples > 65535) return fail(PD_EINVAL, "n_samples out of range");
     int rc = ensure_device(m);
     if (rc) return rc;
     Solve s{};

@@ -65,3 +65,17 @@ def test_uneven_batch_of_single_samples(env):
     for lv, (Q, ns, st) in ((l0, outs[0]), (l1, outs[1])):
         ref = S.beam_problem(lv).run(want_state=False)
         assert Q[0].item() == pytest.approx(ref["Q"], rel=5e-3)
+
+
+def test_batch_beyond_one_launch_is_refused(env):
+    """65535 samples of the level-2 mesh would need 1.5e10 work-items in one
+    step launch (more than a dispatch can count): refused with a message
+    before anything is allocated; the library stays usable."""
+    torch, B = env
+    from paper_2212_04415_amd import pd
+    lv = dataclasses.replace(W.level(2), n_steps=1)
+    mesh = B.Mesh.for_level(lv)
+    with pytest.raises(pd.PdError, match="exceed one launch"):
+        B.run_batch([B.BatchItem(mesh, B.make_params(lv), 65535)])
+    (Q, ns, st), = B.run_batch([B.BatchItem(mesh, B.make_params(lv), 2)])
+    assert torch.all(st == 0)

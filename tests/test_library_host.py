@@ -167,3 +167,19 @@ def test_mesh_size_limit_is_the_kernels_addressing_limit():
         else:
             assert rc == pd.PD_EINVAL
             assert "too large" in pd.pd_last_error()
+
+
+def test_force_eval_sample_count_is_bounded():
+    """Sample counts outside 1..65535 are refused before any device work."""
+    from paper_2212_04415_amd import beam as B
+    lv = W.level(0)
+    rc, h = build(lv.beam, lv.dx)
+    assert rc == pd.PD_OK
+    try:
+        p = B.make_params(lv)
+        buf = (C.c_double * 3)()
+        for n in (0, 65536):
+            assert pd.lib().pd_force_eval(h, C.byref(p), n, buf, buf, None) == pd.PD_EINVAL
+            assert "n_samples" in pd.pd_last_error()
+    finally:
+        pd.lib().pd_free_mesh(h)
