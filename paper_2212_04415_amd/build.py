@@ -84,7 +84,8 @@ def build(verbose: bool = False) -> str:
         if verbose:
             for c in cmds:
                 print(" ".join(c), flush=True)
-        with ThreadPoolExecutor(max_workers=min(len(cmds), max(1, os.cpu_count() or 1))) as ex:
+        # one hipcc per source, at most 16 at once (a shared host's CPU share)
+        with ThreadPoolExecutor(max_workers=min(len(cmds), 16, max(1, os.cpu_count() or 1))) as ex:
             remarks = "".join(f.result() for f in [ex.submit(_compile, c) for c in cmds])
         res = {k: v for k, v in kernel_resources(remarks).items() if "step_kernel" in k}
         spilled = [k for k, v in res.items() if "step_kernelIf" in k and v.get("VGPRSpill", 0) > 0]
