@@ -50,7 +50,7 @@ enum {
 
 enum { PD_LAW_EXPLIN = 0, PD_LAW_TRILINEAR = 1 };
 enum { PD_FP32 = 0, PD_FP64 = 1 };
-enum { PD_ACC_KAHAN = 0, PD_ACC_PLAIN = 1 };
+enum { PD_ACC_KAHAN = 0, PD_ACC_PLAIN = 1, PD_ACC_STATE_ONLY = 2, PD_ACC_FORCES_ONLY = 3 };
 enum { PD_FIELD_S0 = 0, PD_FIELD_C = 1, PD_FIELD_GF = 2 };
 enum { PD_DTYPE_F32 = 0, PD_DTYPE_F64 = 1 };
 /* Launch shapes of the step kernel: nodes per block as an x-by-y-by-z brick
@@ -106,8 +106,12 @@ typedef struct {
  * (force density per velocity); dt: time step; du: load-pad displacement
  * increment per step (the pad is at u_z = -n du after step n); n_steps;
  * precision: PD_FP32 (FP32 bond work and Verlet state with compensated
- * accumulation; FP64 reaction) or PD_FP64; accumulate: PD_ACC_KAHAN or
- * PD_ACC_PLAIN (FP32 ablation); record_history: keep R^n for every step;
+ * accumulation; FP64 reaction) or PD_FP64; accumulate (FP32 only):
+ * PD_ACC_KAHAN (compensated force sums and compensated u / vh updates), or
+ * one of the accuracy ablations PD_ACC_PLAIN (neither), PD_ACC_STATE_ONLY
+ * (compensated updates, plain force sums) and PD_ACC_FORCES_ONLY
+ * (compensated force sums, plain updates); the last two take no
+ * micromodulus field (PD_EINVAL); record_history: keep R^n for every step;
  * checkpoint_every: adjoint checkpoint interval (0 = library default). */
 typedef struct {
     double E, rho, GF, s0, k, alpha;
@@ -239,8 +243,8 @@ PD_API int pd_autotune(pd_mesh m, const pd_params *p, int64_t n_samples, void *s
 
 /* Pins the launch shape of every later run on this mesh (PD_SHAPE_AUTO
  * restores tuning).  Shapes a configuration cannot use fall back to one it
- * can (FP64: PD_SHAPE_GLOBAL_256; PD_ACC_PLAIN: the 16x4x4 brick or the
- * global shape).  Fails with PD_EINVAL for an unknown
+ * can (FP64: PD_SHAPE_GLOBAL_256; the ablations other than PD_ACC_KAHAN:
+ * the 16x4x4 brick or the global shape).  Fails with PD_EINVAL for an unknown
  * shape. */
 PD_API int pd_set_launch_shape(pd_mesh m, int32_t shape);
 

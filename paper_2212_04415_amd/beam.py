@@ -89,7 +89,8 @@ def make_params(level=None, *, precision="f32", accumulate="kahan", E=None, rho=
     p.du = level.du if du is None else du
     p.n_steps = level.n_steps if n_steps is None else n_steps
     p.precision = {"f32": pd.PD_FP32, "f64": pd.PD_FP64}[precision]
-    p.accumulate = {"kahan": pd.PD_ACC_KAHAN, "plain": pd.PD_ACC_PLAIN}[accumulate]
+    p.accumulate = {"kahan": pd.PD_ACC_KAHAN, "plain": pd.PD_ACC_PLAIN, "state_only": pd.PD_ACC_STATE_ONLY,
+                    "forces_only": pd.PD_ACC_FORCES_ONLY}[accumulate]
     p.record_history = 1 if record_history else 0
     p.checkpoint_every = checkpoint_every
     return p

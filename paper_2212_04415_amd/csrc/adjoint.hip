@@ -233,11 +233,11 @@ static int qoi_grad(pd_mesh_s *m, const pd_params *p, const double *s0_dev, cons
     const int64_t N = p->n_steps;
     if (N < 1) return fail(PD_EINVAL, "n_steps must be positive for a gradient");
     const int64_t K = p->checkpoint_every > 0 ? p->checkpoint_every : 200;
-    const bool kahan = sizeof(T) == 4 && p->accumulate == PD_ACC_KAHAN;
-    if ((rc = alloc_run(m, 1, sizeof(T) == 8, kahan, c_dev != nullptr, false, N, s.b, true))) {
+    if ((rc = alloc_run(m, 1, sizeof(T) == 8, p->accumulate, c_dev != nullptr, false, N, s.b, true))) {
         s.b.release();
         return rc;
     }
+    const bool kahan = s.b.comp_state;   // the forward carries compensation arrays to checkpoint
     struct Release {
         RunBuffers &b;
         ~Release() { b.release(); }

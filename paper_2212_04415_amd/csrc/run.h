@@ -125,6 +125,8 @@ static unsigned blocks_for(int64_t n, int b = 256)
 struct RunBuffers {
     int S = 0;
     bool f64 = false, kahan = true, has_c = false, has_g = false;
+    int acc_mode = PD_ACC_KAHAN;   // kahan: the production FP32 kernels (PD_ACC_KAHAN)
+    bool comp_state = true;        // compensated u / vh updates (cu, cvh allocated)
     void *u[2] = {nullptr, nullptr};
     void *vh = nullptr, *cu = nullptr, *cvh = nullptr;
     void *hist = nullptr, *dmask = nullptr, *s0pad = nullptr, *thr = nullptr, *cpad = nullptr, *gpad = nullptr;
@@ -150,20 +152,25 @@ struct RunBuffers {
 
 static int check_launch_size(const pd_mesh_s *m, int64_t S);
 
-static int alloc_run(const pd_mesh_s *m, int S, bool f64, bool kahan, bool has_c, bool want_hist_R, int64_t n_steps,
+// acc: the params' accumulate mode (ignored in FP64, which compensates nothing)
+static int alloc_run(const pd_mesh_s *m, int S, bool f64, int acc, bool has_c, bool want_hist_R, int64_t n_steps,
                      RunBuffers &b, bool outputs, bool has_g = false)
 {
     int rc = check_launch_size(m, S);
     if (rc) return rc;
+    if (!f64 && has_c && (acc == PD_ACC_STATE_ONLY || acc == PD_ACC_FORCES_ONLY))
+        return fail(PD_EINVAL, "the single-compensation ablations take no micromodulus field");
     b.S = S;
     b.f64 = f64;
-    b.kahan = kahan && !f64;
+    b.kahan = !f64 && acc == PD_ACC_KAHAN;
+    b.acc_mode = f64 ? PD_ACC_PLAIN : acc;
+    b.comp_state = !f64 && (acc == PD_ACC_KAHAN || acc == PD_ACC_STATE_ONLY);
     b.has_c = has_c;
     size_t ts = f64 ? 8 : 4, v4 = 4 * ts;
     for (int h = 0; h < 2; ++h)
         if ((rc = b.alloc(&b.u[h], v4 * m->P * S))) return rc;
     if ((rc = b.alloc(&b.vh, v4 * m->M * S))) return rc;
-    if (b.kahan) {
+    if (b.comp_state) {
         if ((rc = b.alloc(&b.cu, v4 * m->M * S))) return rc;
         if ((rc = b.alloc(&b.cvh, v4 * m->M * S))) return rc;
     }
@@ -261,6 +268,7 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     a.vh = (V4 *)b.vh;
     a.cu = (V4 *)b.cu;
     a.cvh = (V4 *)b.cvh;
+    a.acc_mode = b.acc_mode;
     a.hist = (T *)b.hist;
     a.dmask = (uint4 *)b.dmask;
     a.s0pad = (const T *)b.s0pad;
@@ -349,7 +357,7 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
                                              -s.p.du / m->d.dx);
     int64_t nv = 4 * m->M * S;
     fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.vh, nv, T(0));
-    if (s.b.kahan) {
+    if (s.b.comp_state) {
         fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.cu, nv, T(0));
         fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.cvh, nv, T(0));
     }
@@ -373,7 +381,7 @@ static int check_params(const pd_mesh_s *m, const pd_params *p, Material *mat, d
     int rc = material_from_params(m, p, mat);
     if (rc) return rc;
     if (p->precision != PD_FP32 && p->precision != PD_FP64) return fail(PD_EINVAL, "unknown precision");
-    if (p->accumulate != PD_ACC_KAHAN && p->accumulate != PD_ACC_PLAIN) return fail(PD_EINVAL, "unknown accumulate");
+    if (p->accumulate < PD_ACC_KAHAN || p->accumulate > PD_ACC_FORCES_ONLY) return fail(PD_EINVAL, "unknown accumulate");
     double dtc = stability_limit(m, p->rho, mat->c_ref * c_max_rel);
     if (p->dt > dtc)
         return fail(PD_EUNSTABLE, "dt %.6g s exceeds the explicit stability limit %.6g s", p->dt, dtc);

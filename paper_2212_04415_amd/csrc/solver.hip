@@ -188,7 +188,7 @@ int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double
     s.n_steps = 0;
     bool f64 = p->precision == PD_FP64;
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = alloc_run(m, (int)n_samples, f64, p->accumulate == PD_ACC_KAHAN, m->d_c != nullptr, false, 0, s.b, true,
+    if ((rc = alloc_run(m, (int)n_samples, f64, p->accumulate, m->d_c != nullptr, false, 0, s.b, true,
                         m->d_gf != nullptr))) {
         s.b.release();
         return rc;
@@ -253,7 +253,7 @@ int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out)
         return rc;
     }
     bool f64 = p->precision == PD_FP64;
-    rc = alloc_run(m, 1, f64, p->accumulate == PD_ACC_KAHAN, m->d_c != nullptr, p->record_history != 0, p->n_steps,
+    rc = alloc_run(m, 1, f64, p->accumulate, m->d_c != nullptr, p->record_history != 0, p->n_steps,
                    r->s.b, true, m->d_gf != nullptr);
     if (!rc) rc = f64 ? setup_solve<double>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream, m->d_gf, m->M)
                       : setup_solve<float>(r->s, m->d_s0, m->M, m->d_c, m->M, r->stream, m->d_gf, m->M);
@@ -355,7 +355,7 @@ int pd_autotune(pd_mesh m, const pd_params *p, int64_t n_samples, void *stream, 
     s.n_steps = p->n_steps;
     if ((rc = check_params(m, p, &s.mat))) return rc;
     const bool f64 = p->precision == PD_FP64;
-    rc = alloc_run(m, (int)n_samples, f64, p->accumulate == PD_ACC_KAHAN, false, false, 0, s.b, true);
+    rc = alloc_run(m, (int)n_samples, f64, p->accumulate, false, false, 0, s.b, true);
     int best = PD_SHAPE_GLOBAL_256;
     if (!rc) rc = f64 ? setup_solve<double>(s, (const double *)nullptr, 0, (const double *)nullptr, 0, st)
                       : setup_solve<float>(s, (const double *)nullptr, 0, (const double *)nullptr, 0, st);
@@ -407,7 +407,7 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         ticks = std::max(ticks, items[i].params->n_steps * ratio[i]);
     }
     bool f64 = items[0].params->precision == PD_FP64;
-    bool kahan = items[0].params->accumulate == PD_ACC_KAHAN;
+    const int acc = items[0].params->accumulate;
     std::vector<void *> scratch;
     for (int i = 0; i < n_items && !rc; ++i) {
         const pd_batch_item &it = items[i];
@@ -416,7 +416,7 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         s.p = *it.params;
         s.n_steps = it.params->n_steps;
         material_from_params(it.mesh, it.params, &s.mat);
-        rc = alloc_run(it.mesh, (int)it.n_samples, f64, kahan, it.c != nullptr, false, s.n_steps, s.b, false,
+        rc = alloc_run(it.mesh, (int)it.n_samples, f64, acc, it.c != nullptr, false, s.n_steps, s.b, false,
                        it.gf != nullptr);
         if (rc) break;
         s.b.Q = it.qoi;

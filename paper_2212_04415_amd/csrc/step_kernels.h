@@ -122,6 +122,7 @@ struct StepParams {
     int nx, ny, nz, PX, PY, PZ, nsup;
     int nbx, nby;              // bricks along x and y (LDS path)
     int force_only;
+    int acc_mode;              // FP32 without compensation: the ablation run (PD_ACC_*)
     T two_d_b, two_d_g, dt, vload;  // integrator in units of dx
     double du_s;                    // load increment in units of dx
     T gamma_rel, k, alpha, inv1mek, inv1pa;
@@ -863,7 +864,9 @@ __device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int samp
 // Forces and Verlet update of one node, given its neighbour source.  Every
 // lane of the wavefront calls it (the exception pass works across lanes);
 // lanes past the mesh edge pass valid = false and only help that pass.
-template <typename T, bool KAHAN, bool HAS_C, bool PLANE, typename Src>
+// KF: compensated force sums; KS: compensated u / vh updates (both on in the
+// production FP32 path; the ablation kernels take each one separately).
+template <typename T, bool KF, bool KS, bool HAS_C, bool PLANE, typename Src>
 __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab, int sample,
                                           int64_t n, int64_t node, int64_t p, const typename Vec4<T>::t &ui,
                                           bool valid, uint16_t *list)
@@ -878,7 +881,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
     const int gstep = a.gstep;
     const T *__restrict__ Gp = a.gpad + (int64_t)sample * a.P * gstep;
 
-    Acc3<T, KAHAN> acc;
+    Acc3<T, KF> acc;
     acc.zero();
     // A node with a notch-cut bond, or one that has had an exceptional bond
     // (flag -1, kept from then on), runs the masked fast loop plus the
@@ -901,7 +904,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
                 const uint32_t none[4] = {0u, 0u, 0u, 0u};
                 uint32_t unused[4] = {0u, 0u, 0u, 0u};
                 bool flag = false;
-                fast_loop<T, KAHAN, HAS_C, false, PLANE>(a, src, ui, ci, thr, acc, flag, none, unused);
+                fast_loop<T, KF, HAS_C, false, PLANE>(a, src, ui, ci, thr, acc, flag, none, unused);
                 if (flag) {
                     acc.zero();
                     masked = true;
@@ -914,7 +917,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
             const uint32_t skip[4] = {cm.x | d0.x, cm.y | d0.y, cm.z | d0.z, cm.w | d0.w};
             uint32_t exc[4] = {0u, 0u, 0u, 0u};
             bool unused = false;
-            fast_loop<T, KAHAN, HAS_C, true, PLANE>(a, src, ui, ci, thr, acc, unused, skip, exc);
+            fast_loop<T, KF, HAS_C, true, PLANE>(a, src, ui, ci, thr, acc, unused, skip, exc);
             todo[0] = exc[0] & ~cm.x;
             todo[1] = exc[1] & ~cm.y;
             todo[2] = exc[2] & ~cm.z;
@@ -927,7 +930,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
         const T s0i = valid ? S0[p] : T(1);
         const T gi = valid ? ld(Gp, p * gstep, 0u) : T(1);
-        exc_pool<T, KAHAN, HAS_C>(a, src, tab, S0, Hs, Gp, gstep, (uint32_t)p, (uint32_t)node, ui, s0i, ci, gi, todo,
+        exc_pool<T, KF, HAS_C>(a, src, tab, S0, Hs, Gp, gstep, (uint32_t)p, (uint32_t)node, ui, s0i, ci, gi, todo,
                                   dm, acc, list);
     }
     if (!valid) return;
@@ -935,25 +938,25 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         a.dmask[sm] = make_uint4(dm[0], dm[1], dm[2], dm[3]);
     if (a.force_only) {
         double *L = a.L_out + 3 * sm;
-        L[0] = a.LV * ((double)acc.x - (KAHAN ? (double)acc.cx : 0.0));
-        L[1] = a.LV * ((double)acc.y - (KAHAN ? (double)acc.cy : 0.0));
-        L[2] = a.LV * ((double)acc.z - (KAHAN ? (double)acc.cz : 0.0));
+        L[0] = a.LV * ((double)acc.x - (KF ? (double)acc.cx : 0.0));
+        L[1] = a.LV * ((double)acc.y - (KF ? (double)acc.cy : 0.0));
+        L[2] = a.LV * ((double)acc.z - (KF ? (double)acc.cz : 0.0));
         return;
     }
     V4 vh = a.vh[sm];
     V4 un = ui;
     V4 cu, cvh;
-    if constexpr (KAHAN) {
+    if constexpr (KS) {
         cu = a.cu[sm];
         cvh = a.cvh[sm];
     } else {
         cu = V4{};
         cvh = V4{};
     }
-    kick_drift<T, KAHAN>(a, acc.gx(), vh.x, cvh.x, un.x, cu.x);
-    kick_drift<T, KAHAN>(a, acc.gy(), vh.y, cvh.y, un.y, cu.y);
+    kick_drift<T, KS>(a, acc.gx(), vh.x, cvh.x, un.x, cu.x);
+    kick_drift<T, KS>(a, acc.gy(), vh.y, cvh.y, un.y, cu.y);
     if (inf.bc == -1) {
-        kick_drift<T, KAHAN>(a, acc.gz(), vh.z, cvh.z, un.z, cu.z);
+        kick_drift<T, KS>(a, acc.gz(), vh.z, cvh.z, un.z, cu.z);
     } else if (inf.bc == -2) {
         vh.z = a.vload;
         un.z = (T)(-(double)(n + 2) * a.du_s);
@@ -965,14 +968,37 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         cu.z = T(0);
         cvh.z = T(0);
         a.rf[(int64_t)(n & 1) * a.rf_stride + (int64_t)sample * a.nsup + inf.bc] =
-            (double)acc.z - (KAHAN ? (double)acc.cz : 0.0);
+            (double)acc.z - (KF ? (double)acc.cz : 0.0);
     }
     un.w = dirty ? T(-1) : T(1);
     a.u_next[(int64_t)sample * a.P + p] = un;
     a.vh[sm] = vh;
-    if constexpr (KAHAN) {
+    if constexpr (KS) {
         a.cu[sm] = cu;
         a.cvh[sm] = cvh;
+    }
+}
+
+// The node update a kernel runs: both compensations in the production
+// kernels; in the FP32 kernels without them (the accuracy ablation) the
+// launch's mode picks none, the force sums' only or the u / vh updates' only
+// (the last two without a micromodulus field).
+template <typename T, bool KAHAN, bool HAS_C, bool PLANE, typename Src>
+__device__ __forceinline__ void node_step_mode(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
+                                               int sample, int64_t n, int64_t node, int64_t p,
+                                               const typename Vec4<T>::t &ui, bool valid, uint16_t *list)
+{
+    if constexpr (KAHAN) {
+        node_step<T, true, true, HAS_C, PLANE>(a, src, tab, sample, n, node, p, ui, valid, list);
+    } else if constexpr (sizeof(T) == 8 || HAS_C) {
+        node_step<T, false, false, HAS_C, PLANE>(a, src, tab, sample, n, node, p, ui, valid, list);
+    } else {
+        if (a.acc_mode == PD_ACC_STATE_ONLY)
+            node_step<T, false, true, HAS_C, PLANE>(a, src, tab, sample, n, node, p, ui, valid, list);
+        else if (a.acc_mode == PD_ACC_FORCES_ONLY)
+            node_step<T, true, false, HAS_C, PLANE>(a, src, tab, sample, n, node, p, ui, valid, list);
+        else
+            node_step<T, false, false, HAS_C, PLANE>(a, src, tab, sample, n, node, p, ui, valid, list);
     }
 }
 
@@ -1032,7 +1058,7 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         const int64_t p = valid ? (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY : 0;
         const int c = (tx + kHalo) + BR::LX * (ty + YH) + BR::LXY * (tz + kHalo);
         const LdsSrc<T, BR> src{tile, ctile, c};
-        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, tile[c], valid, list);
+        node_step_mode<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, tile[c], valid, list);
     } else {
         __syncthreads();
         const bool valid = t * BR::N + threadIdx.x < a.M;
@@ -1045,7 +1071,7 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
         const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * a.PX + (int64_t)(iz + kHalo) * a.PXY;
         const GlobalSrc<T> src{U, (uint32_t)p * (uint32_t)sizeof(V4), a.PX, a.PXY,
                                HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr, (uint32_t)p * (uint32_t)sizeof(T)};
-        node_step<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, U[p], valid, list);
+        node_step_mode<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, U[p], valid, list);
     }
 }
 

@@ -6,8 +6,10 @@ compensated accumulation, against the FP64 oracle on identical inputs.
 * cracking load (level 0, 400x the literal increment): peak load relative
   error and peak step, FP64 / FP32 compensated / FP32 plain.
 
-The compensated FP32 path must meet the bars the method is held to (u
-relative L2 <= 1e-5, peak within 0.5%); the ablation is reported (printed)."""
+Ablations: no compensation at all, compensated u / vh updates only, and
+compensated force sums only.  The compensated FP32 path must meet the bars
+the method is held to (u relative L2 <= 1e-5, peak within 0.5%); the
+ablations are reported (printed) and held to 1e-4."""
 import concurrent.futures as cf
 import dataclasses
 
@@ -29,6 +31,10 @@ def B():
     return beam
 
 
+# production (both compensations), none, u / vh updates only, force sums only
+ACC_MODES = ("kahan", "plain", "state_only", "forces_only")
+
+
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -42,17 +48,17 @@ def test_elastic_displacement_error_stays_inside_the_bar(B):
     mesh = B.Mesh.for_level(lv)
     rows = []
     for l, ref in zip(lvs, refs):
-        errs = {}
-        for acc in ("kahan", "plain"):
+        errs = []
+        for acc in ACC_MODES:
             out = B.run(mesh, B.make_params(l, precision="f32", accumulate=acc), want_state=True)
-            errs[acc] = rel_l2(out["u"], ref["u"])
-        rows.append((l.n_steps, errs["kahan"], errs["plain"]))
-    print("\nelastic u relative L2 (level 0, literal load): step, FP32 compensated, FP32 plain")
+            errs.append(rel_l2(out["u"], ref["u"]))
+        rows.append((l.n_steps, *errs))
+    print("\nelastic u relative L2 (level 0, literal load): step, FP32 " + ", ".join(ACC_MODES))
     for r in rows:
-        print(f"  {r[0]:5d}  {r[1]:.3e}  {r[2]:.3e}")
-    for n, ek, ep in rows:
+        print(f"  {r[0]:5d}  " + "  ".join(f"{e:.3e}" for e in r[1:]))
+    for n, ek, *abl in rows:
         assert ek <= 1e-5, n
-        assert ep <= 1e-4, n
+        assert all(e <= 1e-4 for e in abl), n
 
 
 def test_cracking_peak_error_per_precision(B):
@@ -60,10 +66,32 @@ def test_cracking_peak_error_per_precision(B):
     ref = S.beam_problem(lv).run(want_state=False)
     mesh = B.Mesh.for_level(lv)
     print(f"\ncracking load, level 0: oracle peak {ref['Q']:.3f} N at step {ref['nstar']}")
-    for prec, acc, tol in (("f64", "kahan", 1e-9), ("f32", "kahan", 5e-3), ("f32", "plain", None)):
+    for prec, acc, tol in (("f64", "kahan", 1e-9), ("f32", "kahan", 5e-3), ("f32", "plain", None),
+                           ("f32", "state_only", None), ("f32", "forces_only", None)):
         out = B.run(mesh, B.make_params(lv, precision=prec, accumulate=acc))
         err = abs(out["Q"] - ref["Q"]) / ref["Q"]
-        print(f"  {prec} {acc:6s}: peak rel err {err:.2e}, peak step {out['nstar']} ({out['nstar'] - ref['nstar']:+d})")
+        print(f"  {prec} {acc:11s}: peak rel err {err:.2e}, peak step {out['nstar']} ({out['nstar'] - ref['nstar']:+d})")
         if tol is not None:
             assert err <= tol
             assert abs(out["nstar"] - ref["nstar"]) <= (2 if prec == "f64" else 0.02 * lv.n_steps)
+
+
+def test_single_compensation_modes_split_the_force_sum_exactly(B):
+    """A force evaluation involves no u / vh update, so compensating only the
+    force sums gives the production forces bit for bit and compensating only
+    the updates gives the uncompensated forces bit for bit; the two
+    single-compensation modes take no micromodulus field."""
+    import torch
+    from paper_2212_04415_amd import pd
+    lv = W.level(0)
+    mesh = B.Mesh.for_level(lv)
+    u = np.stack([W.smooth_displacement(mesh.shape, lv.dx, 3e-6, seed=70 + k) for k in range(2)])
+    u = (u / lv.dx).astype(np.float32).astype(np.float64) * lv.dx
+    L = {acc: B.force_eval(mesh, B.make_params(lv, precision="f32", accumulate=acc), u) for acc in ACC_MODES}
+    assert np.array_equal(L["forces_only"], L["kahan"])
+    assert np.array_equal(L["state_only"], L["plain"])
+    assert not np.array_equal(L["kahan"], L["plain"])
+    c = torch.full((1, mesh.n_nodes), 1.0, dtype=torch.float64, device="cuda")
+    for acc in ("state_only", "forces_only"):
+        with pytest.raises(pd.PdError, match="micromodulus"):
+            B.run_batch([B.BatchItem(mesh, B.make_params(lv, accumulate=acc, n_steps=4), 1, None, c)])
