@@ -308,3 +308,21 @@ def test_level2_batch_matches_oracle(B, torch, level2_refs):
         ref = refs[1 + k]
         assert Q[k].item() == pytest.approx(ref["Q"], rel=5e-3)
         assert abs(ns[k].item() - ref["nstar"]) <= 2
+
+
+def test_reaction_is_the_fp64_sum_of_the_fp32_forces(B):
+    """The reaction reduction on its own: an FP32 run's last reaction R^N is
+    formed from the forces of its final state u^N; evaluating those forces
+    again (bit-identical FP32 arithmetic, no damage in the elastic phase) and
+    summing their z components over the oracle's support set in FP64 gives
+    R^N to 1e-12."""
+    import dataclasses
+    lv = dataclasses.replace(W.level(0), n_steps=600)
+    mesh = B.Mesh.for_level(lv)
+    out = B.run(mesh, B.make_params(lv, precision="f32", record_history=True), want_state=True)
+    assert np.all(out["kappa"] == 0)
+    L = B.force_eval(mesh, B.make_params(lv, precision="f32"), out["u"])[0]
+    prob = S.beam_problem(lv)
+    R = -np.sum(L[prob.support, 2]) * prob.volume
+    assert abs(R) > 1.0
+    assert out["R"][-1] == pytest.approx(R, rel=1e-12)
