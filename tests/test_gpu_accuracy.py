@@ -76,14 +76,16 @@ def test_cracking_peak_error_per_precision(B):
             assert abs(out["nstar"] - ref["nstar"]) <= (2 if prec == "f64" else 0.02 * lv.n_steps)
 
 
-def test_single_compensation_modes_split_the_force_sum_exactly(B):
+@pytest.mark.parametrize("body", ["3d", "plane"])
+def test_single_compensation_modes_split_the_force_sum_exactly(B, body):
     """A force evaluation involves no u / vh update, so compensating only the
     force sums gives the production forces bit for bit and compensating only
-    the updates gives the uncompensated forces bit for bit; the two
-    single-compensation modes take no micromodulus field."""
+    the updates gives the uncompensated forces bit for bit (3D beam at level
+    0, plane-stress specimen at level 1); the two single-compensation modes
+    take no micromodulus field."""
     import torch
     from paper_2212_04415_amd import pd
-    lv = W.level(0)
+    lv = W.level(0) if body == "3d" else W.level2d(1)
     mesh = B.Mesh.for_level(lv)
     u = np.stack([W.smooth_displacement(mesh.shape, lv.dx, 3e-6, seed=70 + k) for k in range(2)])
     u = (u / lv.dx).astype(np.float32).astype(np.float64) * lv.dx
