@@ -169,10 +169,11 @@ static int alloc_run(const pd_mesh_s *m, int S, bool f64, int acc, bool has_c, b
     size_t ts = f64 ? 8 : 4, v4 = 4 * ts;
     for (int h = 0; h < 2; ++h)
         if ((rc = b.alloc(&b.u[h], v4 * m->P * S))) return rc;
-    if ((rc = b.alloc(&b.vh, v4 * m->M * S))) return rc;
+    const size_t v3 = 3 * ts;   // vh, cu, cvh: three components per node
+    if ((rc = b.alloc(&b.vh, v3 * m->M * S))) return rc;
     if (b.comp_state) {
-        if ((rc = b.alloc(&b.cu, v4 * m->M * S))) return rc;
-        if ((rc = b.alloc(&b.cvh, v4 * m->M * S))) return rc;
+        if ((rc = b.alloc(&b.cu, v3 * m->M * S))) return rc;
+        if ((rc = b.alloc(&b.cvh, v3 * m->M * S))) return rc;
     }
     if ((rc = b.alloc(&b.hist, ts * kStencil * m->M * S))) return rc;
     if ((rc = b.alloc(&b.dmask, sizeof(uint4) * m->M * S))) return rc;
@@ -265,9 +266,10 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     StepParams<T> a{};
     a.u_cur = (const V4 *)b.u[parity];
     a.u_next = (V4 *)b.u[parity ^ 1];
-    a.vh = (V4 *)b.vh;
-    a.cu = (V4 *)b.cu;
-    a.cvh = (V4 *)b.cvh;
+    using V3 = typename Vec3<T>::t;
+    a.vh = (V3 *)b.vh;
+    a.cu = (V3 *)b.cu;
+    a.cvh = (V3 *)b.cvh;
     a.acc_mode = b.acc_mode;
     a.hist = (T *)b.hist;
     a.dmask = (uint4 *)b.dmask;
@@ -355,7 +357,7 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
     init_state_kernel<T><<<nb, 256, 0, st>>>((typename Vec4<T>::t *)s.b.u[0], (typename Vec4<T>::t *)s.b.u[1], m->P,
                                              S, m->nx, m->ny, m->nz, m->PX, (int64_t)m->PX * m->PY, m->d_info,
                                              -s.p.du / m->d.dx);
-    int64_t nv = 4 * m->M * S;
+    int64_t nv = 3 * m->M * S;
     fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.vh, nv, T(0));
     if (s.b.comp_state) {
         fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.cu, nv, T(0));

@@ -15,8 +15,8 @@
 //           whose bonds have all stayed inside the plain fast path, -1 a node
 //           that has had a damaged, near-limit or strongly compressed bond.
 //           |flag| is the neighbour-existence weight.
-//   vh    : half-step velocity (dx/s); in FP32 also the compensation terms of
-//           vh and u;
+//   vh    : half-step velocity (dx/s), three components per node; in FP32
+//           also the compensation terms of vh and u (cvh, cu), likewise;
 //   hist  : largest stretch of each bond direction, [122][M], touched only
 //           for damaged bonds (0 until the bond passes its limit);
 //   dmask : per node, one bit per bond direction that has passed its limit;
@@ -79,6 +79,9 @@ constexpr double kSqrtInt[10] = {0.0, 1.0, 1.4142135623730951, 1.732050807568877
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using t = float4; };
 template <> struct Vec4<double> { using t = double4; };
+template <typename T> struct Vec3;
+template <> struct Vec3<float> { using t = float3; };
+template <> struct Vec3<double> { using t = double3; };
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
@@ -94,9 +97,9 @@ struct StepParams {
     using V4 = typename Vec4<T>::t;
     const V4 *u_cur;
     V4 *u_next;
-    V4 *vh;
-    V4 *cu;             // FP32 only: compensation of u
-    V4 *cvh;            // FP32 only: compensation of vh
+    typename Vec3<T>::t *vh;
+    typename Vec3<T>::t *cu;    // FP32 only: compensation of u
+    typename Vec3<T>::t *cvh;   // FP32 only: compensation of vh
     T *hist;            // [S][122][M]
     uint4 *dmask;       // [S][M] damaged-bond bits, one per slot
     const T *s0pad;     // [S][P]
@@ -943,15 +946,16 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         L[2] = a.LV * ((double)acc.z - (KF ? (double)acc.cz : 0.0));
         return;
     }
-    V4 vh = a.vh[sm];
+    using V3 = typename Vec3<T>::t;
+    V3 vh = a.vh[sm];
     V4 un = ui;
-    V4 cu, cvh;
+    V3 cu, cvh;
     if constexpr (KS) {
         cu = a.cu[sm];
         cvh = a.cvh[sm];
     } else {
-        cu = V4{};
-        cvh = V4{};
+        cu = V3{};
+        cvh = V3{};
     }
     kick_drift<T, KS>(a, acc.gx(), vh.x, cvh.x, un.x, cu.x);
     kick_drift<T, KS>(a, acc.gy(), vh.y, cvh.y, un.y, cu.y);
