@@ -110,13 +110,16 @@ static __global__ void init_qoi_kernel(double *Q, int64_t *nstar, int32_t *statu
     }
 }
 
-// Blocks for n elements, capped so that a dispatch's work-item count stays
-// far inside its 32-bit range (the history of a large batch alone can hold
-// more than 2^32 values).  Kernels over several samples' arrays loop with a
-// grid stride; the cap (2^28 threads) is above the largest padded grid of one
-// sample, so per-sample and per-node kernels never reach it.
+// Blocks for one thread per element (kernels over one sample's nodes or
+// cells, or over samples: at most 2^27 elements, far inside a dispatch's
+// 32-bit work-item count).
+static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Blocks for a grid-stride kernel over n elements: capped at 2^20 blocks
+// (2^28 threads), since the arrays of a large batch (its damage history
+// alone) can hold more than 2^32 values.
 constexpr int64_t kMaxBlocks = int64_t(1) << 20;
-static unsigned blocks_for(int64_t n, int b = 256)
+static unsigned stride_blocks(int64_t n, int b = 256)
 {
     return (unsigned)std::min<int64_t>((n + b - 1) / b, kMaxBlocks);
 }
@@ -353,27 +356,27 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
 {
     const pd_mesh_s *m = s.m;
     int64_t S = s.b.S;
-    unsigned nb = blocks_for(m->P * S);
+    unsigned nb = stride_blocks(m->P * S);
     init_state_kernel<T><<<nb, 256, 0, st>>>((typename Vec4<T>::t *)s.b.u[0], (typename Vec4<T>::t *)s.b.u[1], m->P,
                                              S, m->nx, m->ny, m->nz, m->PX, (int64_t)m->PX * m->PY, m->d_info,
                                              -s.p.du / m->d.dx);
     int64_t nv = 3 * m->M * S;
-    fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.vh, nv, T(0));
+    fill_kernel<T><<<stride_blocks(nv), 256, 0, st>>>((T *)s.b.vh, nv, T(0));
     if (s.b.comp_state) {
-        fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.cu, nv, T(0));
-        fill_kernel<T><<<blocks_for(nv), 256, 0, st>>>((T *)s.b.cvh, nv, T(0));
+        fill_kernel<T><<<stride_blocks(nv), 256, 0, st>>>((T *)s.b.cu, nv, T(0));
+        fill_kernel<T><<<stride_blocks(nv), 256, 0, st>>>((T *)s.b.cvh, nv, T(0));
     }
     int64_t nh = (int64_t)kStencil * m->M * S;
-    fill_kernel<T><<<blocks_for(nh), 256, 0, st>>>((T *)s.b.hist, nh, T(0));
-    fill_kernel<uint32_t><<<blocks_for(4 * m->M * S), 256, 0, st>>>((uint32_t *)s.b.dmask, 4 * m->M * S, 0u);
+    fill_kernel<T><<<stride_blocks(nh), 256, 0, st>>>((T *)s.b.hist, nh, T(0));
+    fill_kernel<uint32_t><<<stride_blocks(4 * m->M * S), 256, 0, st>>>((uint32_t *)s.b.dmask, 4 * m->M * S, 0u);
     if (!s.b.has_g) fill_kernel<T><<<1, 256, 0, st>>>((T *)s.b.gpad, 1, T(1));
     fields_kernel<T, In><<<nb, 256, 0, st>>>((T *)s.b.s0pad, (T *)s.b.cpad, s.b.has_g ? (T *)s.b.gpad : nullptr, s0, c,
                                              s.b.has_g ? gf : nullptr, s.p.s0,
                                              1.0 / s.mat.c_ref, 1.0 / s.p.GF, m->P, m->M, S, m->nx, m->ny, m->nz,
                                              m->PX, (int64_t)m->PX * m->PY, s0_stride, c_stride, gf_stride);
-    threshold_kernel<T><<<blocks_for(m->M * S), 256, 0, st>>>((T *)s.b.thr, (const T *)s.b.s0pad, m->P, m->M, S,
+    threshold_kernel<T><<<stride_blocks(m->M * S), 256, 0, st>>>((T *)s.b.thr, (const T *)s.b.s0pad, m->P, m->M, S,
                                                               m->nx, m->ny, m->PX, (int64_t)m->PX * m->PY);
-    init_qoi_kernel<<<blocks_for(S), 256, 0, st>>>(s.b.Q, s.b.nstar, s.b.status, s.b.step, S);
+    init_qoi_kernel<<<stride_blocks(S), 256, 0, st>>>(s.b.Q, s.b.nstar, s.b.status, s.b.step, S);
     PD_HIP(hipGetLastError());
     return PD_OK;
 }
