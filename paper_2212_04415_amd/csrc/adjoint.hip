@@ -245,7 +245,7 @@ static int qoi_grad(pd_mesh_s *m, const pd_params *p, const double *s0_dev, cons
     if ((rc = setup_solve<T>(s, s0_dev, m->M, c_dev, m->M, st))) return rc;
     s.shape = known_shape(s);
 
-    const size_t ubytes = sizeof(V4) * m->P, vbytes = 3 * sizeof(T) * m->M, hbytes = sizeof(T) * kStencil * m->M;
+    const size_t ubytes = sizeof(V4) * m->P, vbytes = vel_components(m) * sizeof(T) * m->M, hbytes = sizeof(T) * kStencil * m->M;
     const size_t dbytes = sizeof(uint4) * m->M;
     const int64_t n_ck = (N + K - 1) / K;
     DevBuf mem;

@@ -154,6 +154,7 @@ struct RunBuffers {
 };
 
 static int check_launch_size(const pd_mesh_s *m, int64_t S);
+static inline int vel_components(const pd_mesh_s *m);
 
 // acc: the params' accumulate mode (ignored in FP64, which compensates nothing)
 static int alloc_run(const pd_mesh_s *m, int S, bool f64, int acc, bool has_c, bool want_hist_R, int64_t n_steps,
@@ -172,7 +173,7 @@ static int alloc_run(const pd_mesh_s *m, int S, bool f64, int acc, bool has_c, b
     size_t ts = f64 ? 8 : 4, v4 = 4 * ts;
     for (int h = 0; h < 2; ++h)
         if ((rc = b.alloc(&b.u[h], v4 * m->P * S))) return rc;
-    const size_t v3 = 3 * ts;   // vh, cu, cvh: three components per node
+    const size_t v3 = vel_components(m) * ts;   // vh, cu, cvh per node
     if ((rc = b.alloc(&b.vh, v3 * m->M * S))) return rc;
     if (b.comp_state) {
         if ((rc = b.alloc(&b.cu, v3 * m->M * S))) return rc;
@@ -220,6 +221,10 @@ constexpr LaunchShape kPlaneShapes[PD_N_SHAPES] = {
 // A body one node thick has neighbours in the x-z plane only; its step
 // kernels visit the 28 in-plane offsets.
 static inline bool plane_mesh(const pd_mesh_s *m) { return m->ny == 1; }
+
+// Components per node of the velocity and compensation arrays: (x, z) in a
+// body one node thick (its y components stay zero), else (x, y, z).
+static inline int vel_components(const pd_mesh_s *m) { return plane_mesh(m) ? 2 : 3; }
 
 // A step launch covers every (sample, tile) work item with one block; the
 // dispatch counts its work-items in 32 bits, so every shape the solve might
@@ -360,7 +365,7 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
     init_state_kernel<T><<<nb, 256, 0, st>>>((typename Vec4<T>::t *)s.b.u[0], (typename Vec4<T>::t *)s.b.u[1], m->P,
                                              S, m->nx, m->ny, m->nz, m->PX, (int64_t)m->PX * m->PY, m->d_info,
                                              -s.p.du / m->d.dx);
-    int64_t nv = 3 * m->M * S;
+    int64_t nv = vel_components(m) * m->M * S;
     fill_kernel<T><<<stride_blocks(nv), 256, 0, st>>>((T *)s.b.vh, nv, T(0));
     if (s.b.comp_state) {
         fill_kernel<T><<<stride_blocks(nv), 256, 0, st>>>((T *)s.b.cu, nv, T(0));

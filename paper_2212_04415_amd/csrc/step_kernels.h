@@ -15,7 +15,8 @@
 //           whose bonds have all stayed inside the plain fast path, -1 a node
 //           that has had a damaged, near-limit or strongly compressed bond.
 //           |flag| is the neighbour-existence weight.
-//   vh    : half-step velocity (dx/s), three components per node; in FP32
+//   vh    : half-step velocity (dx/s), three components per node (two, x
+//           and z, in a plane body, whose y components stay zero); in FP32
 //           also the compensation terms of vh and u (cvh, cu), likewise;
 //   hist  : largest stretch of each bond direction, [122][M], touched only
 //           for damaged bonds (0 until the bond passes its limit);
@@ -82,6 +83,9 @@ template <> struct Vec4<double> { using t = double4; };
 template <typename T> struct Vec3;
 template <> struct Vec3<float> { using t = float3; };
 template <> struct Vec3<double> { using t = double3; };
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using t = float2; };
+template <> struct Vec2<double> { using t = double2; };
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
@@ -947,18 +951,33 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         return;
     }
     using V3 = typename Vec3<T>::t;
-    V3 vh = a.vh[sm];
+    using V2 = typename Vec2<T>::t;
+    // a plane body stores (x, z) only: its y force, velocity and
+    // displacement are zero throughout
+    auto load3 = [&](const V3 *arr) {
+        if constexpr (PLANE) {
+            const V2 q = ((const V2 *)arr)[sm];
+            return V3{q.x, T(0), q.y};
+        } else {
+            return arr[sm];
+        }
+    };
+    auto store3 = [&](V3 *arr, const V3 &q) {
+        if constexpr (PLANE) ((V2 *)arr)[sm] = V2{q.x, q.z};
+        else arr[sm] = q;
+    };
+    V3 vh = load3(a.vh);
     V4 un = ui;
     V3 cu, cvh;
     if constexpr (KS) {
-        cu = a.cu[sm];
-        cvh = a.cvh[sm];
+        cu = load3(a.cu);
+        cvh = load3(a.cvh);
     } else {
         cu = V3{};
         cvh = V3{};
     }
     kick_drift<T, KS>(a, acc.gx(), vh.x, cvh.x, un.x, cu.x);
-    kick_drift<T, KS>(a, acc.gy(), vh.y, cvh.y, un.y, cu.y);
+    if constexpr (!PLANE) kick_drift<T, KS>(a, acc.gy(), vh.y, cvh.y, un.y, cu.y);
     if (inf.bc == -1) {
         kick_drift<T, KS>(a, acc.gz(), vh.z, cvh.z, un.z, cu.z);
     } else if (inf.bc == -2) {
@@ -976,10 +995,10 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
     }
     un.w = dirty ? T(-1) : T(1);
     a.u_next[(int64_t)sample * a.P + p] = un;
-    a.vh[sm] = vh;
+    store3(a.vh, vh);
     if constexpr (KS) {
-        a.cu[sm] = cu;
-        a.cvh[sm] = cvh;
+        store3(a.cu, cu);
+        store3(a.cvh, cvh);
     }
 }
 
