@@ -24,7 +24,9 @@ TEST INFRASTRUCTURE ONLY.  Plain NumPy / SciPy in FP64.
   E = alpha_E 21.5 GPa (f_c / 10 MPa)^(1/3); f_t = 0.3 MPa (f_ck / MPa)^(2/3)
   with f_ck = max(f_c - 8 MPa, f_ck_min); G_F = 73 N/m (f_c / MPa)^0.18;
   then s0 = f_t / E and c = 12 E / (pi delta^4) (plane stress of thickness
-  t: c = 9 E / (pi t delta^3)).
+  t: c = 9 E / (pi t delta^3)).  fib_properties is parity unpinned: the
+  paper prints none of these relations and nothing independent of them is
+  available to check them against.
 """
 from __future__ import annotations
 
@@ -131,7 +133,8 @@ def weibull_from_gaussian(g, fcm, m):
 
 
 def fib_properties(fc, alpha_E=1.0, delta_f=8.0e6, fck_min=1.0e6):
-    """(E, f_t, G_F) in SI from compressive strength fc (Pa)."""
+    """(E, f_t, G_F) in SI from compressive strength fc (Pa).  Parity
+    unpinned (the relations are a reading of a cited, unprinted code)."""
     fc = np.asarray(fc, dtype=np.float64)
     E = alpha_E * 21.5e9 * (fc / 10.0e6) ** (1.0 / 3.0)
     fck = np.maximum(fc - delta_f, fck_min)

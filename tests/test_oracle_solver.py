@@ -238,3 +238,49 @@ def test_damage_is_irreversible():
             F2 = p.force(u, kappa)[1, 0]
             assert kappa[0] == pytest.approx(s1, rel=1e-9)        # history kept
             assert F2 / F1 == pytest.approx(s2 / s1, rel=1e-8)     # secant unloading
+
+
+def test_uniform_stretch_energy_density_pins_the_3d_micromodulus():
+    """Energy density of an isotropic uniform stretch s = eps at an interior
+    node (appendix A, Eq. bond_stiffness_constant, 3D row): each bond stores
+    w = c s^2 |xi| / 2 per unit volume squared, shared by its two ends, so
+    W_i = (1/2) sum_j w V = (1/4) sum_j f_j s |xi_j| V with f_j the bond's
+    force density per unit volume squared.  The forces here come from the
+    oracle itself, one two-node problem per stencil offset.  In the continuum
+    the same sum over the ball of radius delta is c eps^2 pi delta^4 / 4, and
+    with c = 12 E / (pi delta^4) that is 3 E eps^2: the classical density
+    9 K eps^2 / 2 of an isotropic expansion with K = E / (3 (1 - 2 nu)) at
+    the bond-based Poisson ratio nu = 1/4.  On the lattice the ball is the
+    122 offsets |v|^2 <= 9 with full volumes dx^3, so W_i equals the continuum
+    value times sum |v| / (pi m^4), the lattice sum taken here by brute force
+    over integer offsets.  A slip in the constant, the power of delta, the
+    horizon factor (3.14 against pi: 0.2%) or the volume fails at 1e-12.
+    (A stretch of 1e-2 keeps the cancellation in |xi + eta| - |xi| below
+    1e-13 relative; the bonds stay elastic, s0 = 1.)"""
+    dx, eps = 1e-3, 1e-2
+    delta = W.M_RATIO * dx
+    c = S.micromodulus(E, delta)
+    offsets = [v for v in itertools.product(range(-3, 4), repeat=3) if 0 < sum(a * a for a in v) <= 9]
+    assert len(offsets) == 122
+    W_i = 0.0
+    for v in offsets:
+        xi = np.array(v, dtype=np.float64) * dx
+        p = S.Problem(shape=(2, 1, 1), dx=dx, bond_i=np.array([0]), bond_j=np.array([1]), xi=xi[None, :],
+                      support=np.array([], dtype=np.int64), load=np.array([], dtype=np.int64),
+                      s0=np.full(2, 1.0), c=np.full(2, c), rho=RHO, damping=0.0, dt=1e-7, du=0.0, n_steps=0,
+                      law=S.LAW_TRILINEAR, k=W.SOFT_K, alpha=W.SOFT_ALPHA, GF=W.FRACTURE_ENERGY, delta=delta)
+        u = np.zeros((2, 3))
+        u[1] = eps * xi                       # node 0 at the origin, node 1 at xi
+        s = p.stretch(u)[0]
+        assert s == pytest.approx(eps, rel=1e-13)
+        L = p.force(u)
+        assert np.allclose(L[0], -L[1], rtol=0, atol=1e-12 * np.abs(L).max())
+        f = np.linalg.norm(L[1]) / p.volume   # |L_j| = f V
+        W_i += 0.25 * f * s * np.linalg.norm(xi) * p.volume
+    lattice_ratio = sum(np.sqrt(sum(a * a for a in v)) for v in offsets) / (np.pi * W.M_RATIO ** 4)
+    assert lattice_ratio == pytest.approx(0.933929, abs=5e-7)
+    nu = 0.25
+    K = E / (3 * (1 - 2 * nu))
+    continuum = 4.5 * K * eps ** 2
+    assert continuum == pytest.approx(3 * E * eps ** 2, rel=1e-14)
+    assert W_i == pytest.approx(lattice_ratio * continuum, rel=1e-12)
