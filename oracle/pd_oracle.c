@@ -15,12 +15,21 @@
  *   - support reaction R^n and its running maximum Q, the peak load (section 4, QoI)
  *
  * Every loop runs over the unique bond list in its given order; no fusion,
- * no reordering, no compensation.
+ * no reordering, no compensation.  The bond loop of a force evaluation is cut
+ * into a fixed number of contiguous chunks, each summing into a buffer of its
+ * own, and the buffers are added in chunk order: with OpenMP the chunks run
+ * on the host's cores, and the result is the same for any thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* bond chunks of a force evaluation (fixed: results do not depend on threads) */
+#define PDO_CHUNKS 16
 
 #define PDO_PI 3.14159265358979323846
 #define PDO_LAW_EXPLIN 0
@@ -119,30 +128,82 @@ double pdo_damage(int32_t law, double kappa, double s0, double sc, double k, dou
 
 /* ---------------------------------------------------------------- force */
 
+/* One bond: stretch, damage history (updated in place), force f e V added to
+ * node i and subtracted from node j of the buffer L. */
+static void bond_force(const pdo_problem *p, int64_t b, const double *u, double *kappa, const double *c_b,
+                       const double *s0_b, const double *sc_b, double *L)
+{
+    int32_t i = p->bond_i[b], j = p->bond_j[b];
+    const double *xi = p->xi + 3 * b;
+    double y[3];
+    for (int d = 0; d < 3; ++d) y[d] = xi[d] + (u[3 * j + d] - u[3 * i + d]);
+    double ylen = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    double xlen = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+    double s = (ylen - xlen) / xlen;
+    if (s > kappa[b]) kappa[b] = s;
+    double dmg = pdo_damage(p->law, kappa[b], s0_b[b], sc_b[b], p->k, p->alpha);
+    double f = c_b[b] * (1.0 - dmg) * s;
+    for (int d = 0; d < 3; ++d) {
+        double fd = f * (y[d] / ylen) * p->volume;
+        L[3 * i + d] += fd;
+        L[3 * j + d] -= fd;
+    }
+}
+
 /* One force evaluation: L = sum over bonds of f e V, damage history updated in
- * place.  kappa[b] holds the largest stretch bond b has seen (-inf initially). */
+ * place.  kappa[b] holds the largest stretch bond b has seen (-inf initially).
+ * work: PDO_CHUNKS * 3 * n_nodes doubles (chunk buffers).  A chunk's bonds
+ * touch a contiguous node range [lo, hi] (the bond list is sorted by node),
+ * so only that range of its buffer is cleared and summed. */
 static void force_eval(const pdo_problem *p, const double *u, double *kappa,
                        const double *c_b, const double *s0_b, const double *sc_b,
-                       double *L)
+                       double *L, double *work)
 {
-    memset(L, 0, sizeof(double) * 3 * p->n_nodes);
-    for (int64_t b = 0; b < p->n_bonds; ++b) {
-        int32_t i = p->bond_i[b], j = p->bond_j[b];
-        const double *xi = p->xi + 3 * b;
-        double y[3];
-        for (int d = 0; d < 3; ++d) y[d] = xi[d] + (u[3 * j + d] - u[3 * i + d]);
-        double ylen = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-        double xlen = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
-        double s = (ylen - xlen) / xlen;
-        if (s > kappa[b]) kappa[b] = s;
-        double dmg = pdo_damage(p->law, kappa[b], s0_b[b], sc_b[b], p->k, p->alpha);
-        double f = c_b[b] * (1.0 - dmg) * s;
-        for (int d = 0; d < 3; ++d) {
-            double fd = f * (y[d] / ylen) * p->volume;
-            L[3 * i + d] += fd;
-            L[3 * j + d] -= fd;
+    const int64_t M = p->n_nodes, M3 = 3 * M, nb = p->n_bonds;
+    int64_t lo[PDO_CHUNKS], hi[PDO_CHUNKS];
+#pragma omp parallel for schedule(static, 1)
+    for (int ch = 0; ch < PDO_CHUNKS; ++ch) {
+        double *Lc = work + (int64_t)ch * M3;
+        const int64_t b0 = nb * ch / PDO_CHUNKS, b1 = nb * (ch + 1) / PDO_CHUNKS;
+        int64_t a = M, z = -1;
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t i = p->bond_i[b], j = p->bond_j[b];
+            if (i < a) a = i;
+            if (j < a) a = j;
+            if (i > z) z = i;
+            if (j > z) z = j;
         }
+        lo[ch] = a;
+        hi[ch] = z;
+        if (z >= a) memset(Lc + 3 * a, 0, sizeof(double) * 3 * (z - a + 1));
+        for (int64_t b = b0; b < b1; ++b) bond_force(p, b, u, kappa, c_b, s0_b, sc_b, Lc);
     }
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < M3; ++q) {
+        const int64_t node = q / 3;
+        double acc = 0.0;
+        for (int ch = 0; ch < PDO_CHUNKS; ++ch)
+            if (node >= lo[ch] && node <= hi[ch]) acc += work[(int64_t)ch * M3 + q];
+        L[q] = acc;
+    }
+}
+
+/* Threads of the force loop (OpenMP builds; 1 otherwise).  n <= 0 leaves the
+ * setting unchanged.  Returns the number now in use. */
+int pdo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+static double *chunk_work(const pdo_problem *p)
+{
+    return malloc(sizeof(double) * PDO_CHUNKS * 3 * (size_t)(p->n_nodes > 0 ? p->n_nodes : 1));
 }
 
 static void bond_params(const pdo_problem *p, double *c_b, double *s0_b, double *sc_b)
@@ -164,15 +225,15 @@ int pdo_force(const pdo_problem *p, const double *u, double *kappa, double *L)
 {
     int64_t nb = p->n_bonds;
     double *c_b = malloc(sizeof(double) * nb), *s0_b = malloc(sizeof(double) * nb),
-           *sc_b = malloc(sizeof(double) * nb), *kap = NULL;
-    if (!c_b || !s0_b || !sc_b) return -2;
+           *sc_b = malloc(sizeof(double) * nb), *kap = NULL, *work = chunk_work(p);
+    if (!c_b || !s0_b || !sc_b || !work) return -2;
     bond_params(p, c_b, s0_b, sc_b);
     if (!kappa) {
         kap = malloc(sizeof(double) * nb);
         for (int64_t b = 0; b < nb; ++b) kap[b] = -INFINITY;
     }
-    force_eval(p, u, kappa ? kappa : kap, c_b, s0_b, sc_b, L);
-    free(c_b); free(s0_b); free(sc_b); free(kap);
+    force_eval(p, u, kappa ? kappa : kap, c_b, s0_b, sc_b, L, work);
+    free(c_b); free(s0_b); free(sc_b); free(kap); free(work);
     return 0;
 }
 
@@ -211,9 +272,9 @@ int pdo_run(const pdo_problem *p, const double *u_init, const double *v_init,
     double *L = calloc(3 * M, sizeof(double));
     double *kappa = malloc(sizeof(double) * nb);
     double *c_b = malloc(sizeof(double) * nb), *s0_b = malloc(sizeof(double) * nb),
-           *sc_b = malloc(sizeof(double) * nb);
+           *sc_b = malloc(sizeof(double) * nb), *work = chunk_work(p);
     unsigned char *fixed_z = calloc(M, 1);
-    if (!u || !v || !L || !kappa || !c_b || !s0_b || !sc_b || !fixed_z) return -2;
+    if (!u || !v || !L || !kappa || !c_b || !s0_b || !sc_b || !fixed_z || !work) return -2;
     if (u_init) memcpy(u, u_init, sizeof(double) * 3 * M);
     if (v_init) memcpy(v, v_init, sizeof(double) * 3 * M);
     for (int64_t b = 0; b < nb; ++b) kappa[b] = kappa_init ? kappa_init[b] : -INFINITY;
@@ -222,7 +283,7 @@ int pdo_run(const pdo_problem *p, const double *u_init, const double *v_init,
     for (int64_t a = 0; a < p->n_load; ++a) fixed_z[p->load[a]] = 1;
 
     /* the initial force of the (possibly pre-displaced) body */
-    force_eval(p, u, kappa, c_b, s0_b, sc_b, L);
+    force_eval(p, u, kappa, c_b, s0_b, sc_b, L, work);
 
     double h = p->dt / (2.0 * p->rho);
     double Q = -INFINITY;
@@ -242,7 +303,7 @@ int pdo_run(const pdo_problem *p, const double *u_init, const double *v_init,
             u[3 * p->load[a] + 2] = p->load_offset - (double)(n + 1) * p->du;
             v[3 * p->load[a] + 2] = -p->du / p->dt;
         }
-        force_eval(p, u, kappa, c_b, s0_b, sc_b, L);
+        force_eval(p, u, kappa, c_b, s0_b, sc_b, L, work);
         for (int64_t i = 0; i < M; ++i)
             for (int d = 0; d < 3; ++d) {
                 if (d == 2 && fixed_z[i]) continue;
@@ -258,7 +319,7 @@ int pdo_run(const pdo_problem *p, const double *u_init, const double *v_init,
     if (u_out) memcpy(u_out, u, sizeof(double) * 3 * M);
     if (v_out) memcpy(v_out, v, sizeof(double) * 3 * M);
     if (kappa_out) memcpy(kappa_out, kappa, sizeof(double) * nb);
-    free(u); free(v); free(L); free(kappa); free(c_b); free(s0_b); free(sc_b); free(fixed_z);
+    free(u); free(v); free(L); free(kappa); free(c_b); free(s0_b); free(sc_b); free(fixed_z); free(work);
     return 0;
 }
 
@@ -327,13 +388,13 @@ int pdo_adjoint(const pdo_problem *p, double *Q_out, int64_t *nstar_out, double 
     double *v = calloc(3 * M, sizeof(double)), *L = calloc(3 * M, sizeof(double));
     double *kappa = malloc(sizeof(double) * nb);
     double *c_b = malloc(sizeof(double) * nb), *s0_b = malloc(sizeof(double) * nb),
-           *sc_b = malloc(sizeof(double) * nb);
+           *sc_b = malloc(sizeof(double) * nb), *work = chunk_work(p);
     unsigned char *fixed_z = calloc(M, 1);
     int64_t *ev_start = calloc(N + 2, sizeof(int64_t));
     int64_t ev_cap = 1 << 16, ev_n = 0;
     int32_t *ev_bond = malloc(sizeof(int32_t) * ev_cap);
     double *ev_old = malloc(sizeof(double) * ev_cap);
-    if (!U || !v || !L || !kappa || !c_b || !s0_b || !sc_b || !fixed_z || !ev_start || !ev_bond || !ev_old)
+    if (!U || !v || !L || !kappa || !c_b || !s0_b || !sc_b || !fixed_z || !ev_start || !ev_bond || !ev_old || !work)
         return -2;
     bond_params(p, c_b, s0_b, sc_b);
     for (int64_t b = 0; b < nb; ++b) kappa[b] = -INFINITY;
@@ -382,7 +443,7 @@ int pdo_adjoint(const pdo_problem *p, double *Q_out, int64_t *nstar_out, double 
                 ++ev_n;
             }
         }
-        force_eval(p, u1, kappa, c_b, s0_b, sc_b, L);
+        force_eval(p, u1, kappa, c_b, s0_b, sc_b, L, work);
         for (int64_t i = 0; i < M; ++i)
             for (int d = 0; d < 3; ++d) {
                 if (d == 2 && fixed_z[i]) continue;
@@ -474,7 +535,7 @@ int pdo_adjoint(const pdo_problem *p, double *Q_out, int64_t *nstar_out, double 
             ub_next[q] = ub[q];
         }
     }
-    free(U); free(v); free(L); free(kappa); free(c_b); free(s0_b); free(sc_b); free(fixed_z);
+    free(U); free(v); free(L); free(kappa); free(c_b); free(s0_b); free(sc_b); free(fixed_z); free(work);
     free(ev_start); free(ev_bond); free(ev_old);
     free(ub_next); free(ub); free(wb); free(Lb); free(kb); free(active);
     return 0;

@@ -33,12 +33,20 @@ LAW_TRILINEAR = 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (no fast-math)."""
+    """Compile the C oracle with gcc (-O2, no fast-math, OpenMP over the
+    force loop's fixed bond chunks)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's force loop for calls made from this thread
+    (n <= 0: unchanged); returns the count in use.  Results do not depend on
+    it."""
+    return int(lib().pdo_set_threads(int(n)))
 
 
 class _Problem(C.Structure):
@@ -81,6 +89,8 @@ def lib():
         L.pdo_keep_derivs.argtypes = [C.c_int32, d, d, d, d, d, C.c_void_p]
         L.pdo_adjoint.restype = C.c_int
         L.pdo_adjoint.argtypes = [P, C.POINTER(d), C.POINTER(i64), C.c_void_p, C.c_void_p]
+        L.pdo_set_threads.restype = C.c_int
+        L.pdo_set_threads.argtypes = [C.c_int]
         L.pdo_run.restype = C.c_int
         L.pdo_run.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(d), C.POINTER(i64),
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
