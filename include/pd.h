@@ -207,7 +207,8 @@ PD_API int pd_free_run(pd_run_h r);
  * c (micromodulus, device or NULL), gf (fracture energy in N/m, device or
  * NULL = homogeneous p->GF); outputs qoi (device FP64 [n_samples]), nstar (device
  * int64 [n_samples], nullable), status (device int32 [n_samples], nullable;
- * PD_OK or PD_ENONFINITE).  Enqueued on stream and synchronised before it
+ * PD_OK or PD_ENONFINITE), u_out (device FP64 [n_samples][n_nodes][3],
+ * nullable: each sample's displacement after its last step, in metres).  Enqueued on stream and synchronised before it
  * returns (the library's work buffers are released).  All items share
  * precision and accumulate.  n_samples per item: 1 to 65535, and at most as
  * many as one step launch over the mesh's tiles can hold (2^32 - 1
@@ -223,6 +224,7 @@ typedef struct {
     double *qoi;
     int64_t *nstar;
     int32_t *status;
+    double *u_out;
 } pd_batch_item;
 
 PD_API int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream);

@@ -98,6 +98,24 @@ def lib():
     return _lib
 
 
+def run_many(problems, fn=None, **kw):
+    """Runs problems[k].run(**kw) (or fn(problems[k])) for every k, in order of
+    the list.  Few large problems run one after the other, each on all of the
+    host's cores; many run side by side in a thread pool whose workers use one
+    core each (the C loop releases the GIL)."""
+    import concurrent.futures as cf
+    call = fn if fn is not None else (lambda p: p.run(**kw))
+    cores = max(1, set_threads(0))
+    if len(problems) < cores:
+        return [call(p) for p in problems]
+
+    def one(p):
+        set_threads(1)
+        return call(p)
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        return list(ex.map(one, problems))
+
+
 def micromodulus(E, delta):
     """3D bond stiffness constant, appendix A Eq. bond_stiffness_constant."""
     return 12.0 * E / (np.pi * delta ** 4)

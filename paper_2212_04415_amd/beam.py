@@ -132,10 +132,13 @@ class BatchItem:
     s0: object = None          # torch tensor [S][M] on the device, or None
     c: object = None           # micromodulus (absolute), or None
     gf: object = None          # fracture energy (N/m), or None
+    want_u: bool = False       # also return each sample's final displacement [S][M][3]
 
 
 def run_batch(items: Sequence[BatchItem], stream=None):
-    """Returns a list of (Q, nstar, status) torch tensors, one triple per item."""
+    """Returns a list of (Q, nstar, status) torch tensors, one triple per item
+    (a fourth tensor, the final displacements [S][M][3], for items with
+    want_u)."""
     import torch
     dev = torch.device("cuda")
     arr = (pd.pd_batch_item * len(items))()
@@ -151,12 +154,14 @@ def run_batch(items: Sequence[BatchItem], stream=None):
             dtype = pd.PD_DTYPE_F32 if f.dtype == torch.float32 else pd.PD_DTYPE_F64
         assert all(f.dtype == given[0].dtype for f in given)
         keep.append(it.params)
+        u = torch.empty((it.n_samples, it.mesh.n_nodes, 3), dtype=torch.float64, device=dev) if it.want_u else None
         arr[i] = pd.pd_batch_item(it.mesh.h, C.pointer(it.params), it.n_samples,
                                   it.s0.data_ptr() if it.s0 is not None else None,
                                   it.c.data_ptr() if it.c is not None else None,
                                   it.gf.data_ptr() if it.gf is not None else None, dtype,
-                                  Q.data_ptr(), ns.data_ptr(), st.data_ptr())
-        outs.append((Q, ns, st))
+                                  Q.data_ptr(), ns.data_ptr(), st.data_ptr(),
+                                  u.data_ptr() if u is not None else None)
+        outs.append((Q, ns, st) if u is None else (Q, ns, st, u))
     pd.pd_run_batch(arr, len(items), _stream_ptr(stream))
     return outs
 
@@ -255,13 +260,22 @@ def autotune(mesh: Mesh, params, n_samples: int, stream=None):
     return dict(shape=shape.value, us_per_step=us)
 
 
-def qoi_grad(mesh: Mesh, params, s0=None, c=None, stream=None):
+def qoi_grad(mesh: Mesh, params, s0=None, c=None, stream=None, as_tensors=False):
     """Peak reaction, its step, and dQ/ds0, dQ/dc per node (pd_qoi_grad).
-    s0 / c: per-node fields (array-like, FP64) or None for homogeneous."""
+    s0 / c: per-node fields (FP64 device tensors are passed as they are; other
+    array-likes are uploaded once) or None for homogeneous.  The gradients come
+    back as device tensors with as_tensors, else as NumPy arrays."""
     import torch
     dev = torch.device("cuda")
-    s0_t = None if s0 is None else torch.as_tensor(np.asarray(s0, dtype=np.float64), device=dev).contiguous()
-    c_t = None if c is None else torch.as_tensor(np.asarray(c, dtype=np.float64), device=dev).contiguous()
+
+    def on_device(f):
+        if f is None:
+            return None
+        if isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64:
+            return f.detach().contiguous()
+        return torch.as_tensor(np.asarray(f, dtype=np.float64), device=dev).contiguous()
+
+    s0_t, c_t = on_device(s0), on_device(c)
     g0 = torch.empty(mesh.n_nodes, dtype=torch.float64, device=dev)
     gc = torch.empty(mesh.n_nodes, dtype=torch.float64, device=dev)
     Q = C.c_double()
@@ -269,6 +283,8 @@ def qoi_grad(mesh: Mesh, params, s0=None, c=None, stream=None):
     pd.pd_qoi_grad(mesh.h, C.byref(params), s0_t.data_ptr() if s0_t is not None else None,
                    c_t.data_ptr() if c_t is not None else None, g0.data_ptr(), gc.data_ptr(),
                    C.byref(Q), C.byref(ns), _stream_ptr(stream))
+    if as_tensors:
+        return dict(Q=Q.value, nstar=ns.value, dQ_ds0=g0, dQ_dc=gc)
     return dict(Q=Q.value, nstar=ns.value, dQ_ds0=g0.cpu().numpy(), dQ_dc=gc.cpu().numpy())
 
 
@@ -287,17 +303,25 @@ def mlmc_estimate(level_sums, stream=None):
 
 def peak_load_function():
     """torch.autograd.Function: peak reaction of one sample as a function of
-    its per-node s0 and c fields (FP64 device tensors); backward applies the
-    hand-written adjoint (pd_qoi_grad)."""
+    its per-node s0 and c fields (FP64 device tensors [n_nodes]).  When a
+    gradient is wanted the forward runs the hand-written adjoint
+    (pd_qoi_grad: the forward solve, then the reverse sweep) and keeps
+    dQ/ds0 and dQ/dc on the device for backward; otherwise it runs the
+    forward solve alone (pd_run_batch).  The fields never leave the device."""
     import torch
 
     class PeakLoad(torch.autograd.Function):
         @staticmethod
         def forward(ctx, s0, c, mesh, params):
-            out = qoi_grad(mesh, params, s0.detach().cpu().numpy(), c.detach().cpu().numpy())
-            ctx.save_for_backward(torch.as_tensor(out["dQ_ds0"], device=s0.device),
-                                  torch.as_tensor(out["dQ_dc"], device=c.device))
-            return torch.tensor(out["Q"], dtype=torch.float64, device=s0.device)
+            if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+                out = qoi_grad(mesh, params, s0, c, as_tensors=True)
+                ctx.save_for_backward(out["dQ_ds0"], out["dQ_dc"])
+                return torch.tensor(out["Q"], dtype=torch.float64, device=s0.device)
+            dtype = s0.dtype
+            item = BatchItem(mesh, params, 1, s0.detach().reshape(1, -1).contiguous(),
+                             c.detach().to(dtype).reshape(1, -1).contiguous())
+            (Q, ns, st), = run_batch([item])
+            return Q[0].clone()
 
         @staticmethod
         def backward(ctx, g):

@@ -110,6 +110,26 @@ static __global__ void init_qoi_kernel(double *Q, int64_t *nstar, int32_t *statu
     }
 }
 
+// Final displacement of every sample of a solve as FP64 [S][M][3] in metres
+// (u in units of dx, from the padded ping-pong buffer that holds u^N).
+template <typename T>
+__global__ void export_u_kernel(const typename Vec4<T>::t *u, int64_t P, int64_t M, int64_t S, int nx, int ny,
+                                int PX, int64_t PXY, double dx, double *out)
+{
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < M * S;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sample = g / M, node = g % M;
+        const int ix = (int)(node % nx);
+        const int64_t r = node / nx;
+        const int iy = (int)(r % ny), iz = (int)(r / ny);
+        const int64_t p = (int64_t)(ix + kHalo) + (int64_t)(iy + kHalo) * PX + (int64_t)(iz + kHalo) * PXY;
+        const typename Vec4<T>::t v = u[sample * P + p];
+        out[3 * g + 0] = (double)v.x * dx;
+        out[3 * g + 1] = (double)v.y * dx;
+        out[3 * g + 2] = (double)v.z * dx;
+    }
+}
+
 // Blocks for one thread per element (kernels over one sample's nodes or
 // cells, or over samples: at most 2^27 elements, far inside a dispatch's
 // 32-bit work-item count).
@@ -352,6 +372,23 @@ static inline void launch_step(const Solve &s, int k_local, hipStream_t st, doub
 static void launch_advance(const Solve &s, int64_t by, hipStream_t st)
 {
     advance_kernel<<<blocks_for(s.b.S), 256, 0, st>>>(s.b.step, s.b.S, by);
+}
+
+// Copies a finished solve's displacement u^N (the input of its last step
+// launch, in buffer (N - 1) & 1) to out, FP64 [S][M][3] in metres.
+static void launch_export_u(const Solve &s, double *out, hipStream_t st)
+{
+    const pd_mesh_s *m = s.m;
+    const int parity = s.n_steps > 0 ? (int)((s.n_steps - 1) & 1) : 0;
+    const int64_t n = m->M * s.b.S;
+    if (s.b.f64)
+        export_u_kernel<double><<<stride_blocks(n), 256, 0, st>>>((const double4 *)s.b.u[parity], m->P, m->M, s.b.S,
+                                                                  m->nx, m->ny, m->PX, (int64_t)m->PX * m->PY,
+                                                                  m->d.dx, out);
+    else
+        export_u_kernel<float><<<stride_blocks(n), 256, 0, st>>>((const float4 *)s.b.u[parity], m->P, m->M, s.b.S,
+                                                                 m->nx, m->ny, m->PX, (int64_t)m->PX * m->PY,
+                                                                 m->d.dx, out);
 }
 
 // s0 / c: device [S][M] fields of type In, or null (homogeneous)

@@ -497,6 +497,8 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
             else launch_step<float>(solves[i], 0, st);
         }
     }
+    for (int i = 0; !rc && i < n_items; ++i)
+        if (items[i].u_out) launch_export_u(solves[i], items[i].u_out, st);
     hipError_t e = hipStreamSynchronize(st);
     if (!rc && e != hipSuccess) rc = hip_fail(e, "batch");
     if (exec) (void)hipGraphExecDestroy(exec);

@@ -57,7 +57,7 @@ class pd_fib_params(C.Structure):
 class pd_batch_item(C.Structure):
     _fields_ = [("mesh", C.c_void_p), ("params", C.POINTER(pd_params)), ("n_samples", C.c_int64),
                 ("s0", C.c_void_p), ("c", C.c_void_p), ("gf", C.c_void_p), ("field_dtype", C.c_int32),
-                ("qoi", C.c_void_p), ("nstar", C.c_void_p), ("status", C.c_void_p)]
+                ("qoi", C.c_void_p), ("nstar", C.c_void_p), ("status", C.c_void_p), ("u_out", C.c_void_p)]
 
 
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double

@@ -10,7 +10,6 @@ Ablations: no compensation at all, compensated u / vh updates only, and
 compensated force sums only.  The compensated FP32 path must meet the bars
 the method is held to (u relative L2 <= 1e-5, peak within 0.5%); the
 ablations are reported (printed) and held to 1e-4."""
-import concurrent.futures as cf
 import dataclasses
 
 import numpy as np
@@ -43,8 +42,7 @@ def test_elastic_displacement_error_stays_inside_the_bar(B):
     lv = W.level(0)
     steps = (1000, 2000, 4000)
     lvs = [dataclasses.replace(lv, n_steps=n) for n in steps]
-    with cf.ThreadPoolExecutor(3) as ex:
-        refs = list(ex.map(lambda l: S.beam_problem(l).run(), lvs))
+    refs = S.run_many([S.beam_problem(l) for l in lvs])
     mesh = B.Mesh.for_level(lv)
     rows = []
     for l, ref in zip(lvs, refs):

@@ -1,6 +1,5 @@
 """The batched MLMC hierarchy on the GPU: coupled pairs, FP64 level sums and
 the estimator, against the oracle's solves and statistics."""
-import concurrent.futures as cf
 
 import numpy as np
 import pytest
@@ -41,8 +40,7 @@ def test_every_solve_matches_the_oracle(run):
             xi = np.concatenate([xi, W.kl_coefficients(2, samples[l + 1], stream=l + 1)])
         fields = OKL.lognormal_field(ob, pos, xi, W.S0_MEAN, W.FIELD_COV)
         jobs += [(l, k, S.beam_problem(lv, s0=fields[k])) for k in range(xi.shape[0])]
-    with cf.ThreadPoolExecutor(8) as ex:
-        refs = list(ex.map(lambda j: j[2].run(want_state=False)["Q"], jobs))
+    refs = [r["Q"] for r in S.run_many([j[2] for j in jobs], want_state=False)]
     for (l, k, _), q in zip(jobs, refs):
         assert out["Q"][l][k] == pytest.approx(q, rel=5e-3), (l, k)
 

@@ -4,8 +4,6 @@ inputs, through the C ABI.
 Tolerances: FP64 GPU runs agree with the oracle to rounding (summation order
 differs); FP32 runs meet the targets the method is held to: elastic-phase
 displacement relative L2 <= 1e-5 and peak load within 0.5%."""
-import concurrent.futures as cf
-
 import numpy as np
 import pytest
 
@@ -37,10 +35,7 @@ def rel_l2(a, b):
 
 
 def oracle_runs(problems, **kw):
-    """Run several oracle problems in parallel threads (the C loop releases
-    the GIL)."""
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(problems))) as ex:
-        return list(ex.map(lambda p: p.run(**kw), problems))
+    return S.run_many(problems, **kw)
 
 
 def bond_force_scale(prob, u):
@@ -82,6 +77,67 @@ def force_error_ok(L_gpu, L_ref, prob, u, precision):
 def fp32_rounded(u, dx):
     """Displacements as the FP32 path stores them (float32, units of dx)."""
     return (u / dx).astype(np.float32).astype(np.float64) * dx
+
+
+def half_stencil():
+    """The library's slot numbering of the 122 bond directions of a node:
+    slot k < 61 is the k-th offset v with 0 < |v|^2 <= 9 whose first non-zero
+    component in (z, y, x) order is positive (z slowest, then y, then x, each
+    ascending), slot 61 + k its negation."""
+    out = []
+    for z in range(0, 4):
+        for y in range(-3, 4):
+            for x in range(-3, 4):
+                r2 = x * x + y * y + z * z
+                if 0 < r2 <= 9 and (z > 0 or (z == 0 and (y > 0 or (y == 0 and x > 0)))):
+                    out.append((x, y, z))
+    assert len(out) == 61
+    return {v: k for k, v in enumerate(out)}
+
+
+def bond_slots(prob):
+    """For every unique oracle bond (i, j): the slot of direction j - i at node
+    i and the slot of direction i - j at node j."""
+    table = half_stencil()
+    v = np.rint(prob.xi / prob.dx).astype(int)
+    ka = np.empty(prob.n_bonds, dtype=np.int64)
+    kb = np.empty(prob.n_bonds, dtype=np.int64)
+    for b, (x, y, z) in enumerate(map(tuple, v)):
+        if (x, y, z) in table:
+            ka[b], kb[b] = table[(x, y, z)], 61 + table[(x, y, z)]
+        else:
+            k = table[(-x, -y, -z)]
+            ka[b], kb[b] = 61 + k, k
+    return ka, kb
+
+
+def check_kappa_per_bond(kappa_gpu, ref, prob, rel):
+    """Damage history bond by bond (appendix A, Eq. exp_damage_parameter; the
+    library keeps kappa of a bond direction once the bond passes its limit
+    stretch, 0 before): every oracle bond past its limit has that kappa in both
+    of its slots to `rel`, every other bond has 0 in both; bonds within `rel`
+    of their limit may go either way.  Returns the number of damaged bonds."""
+    ka, kb = bond_slots(prob)
+    kr = ref["kappa"]
+    s0b = 0.5 * (prob.s0[prob.bond_i] + prob.s0[prob.bond_j])
+    g_a = kappa_gpu[ka, prob.bond_i]
+    g_b = kappa_gpu[kb, prob.bond_j]
+    assert np.array_equal(g_a, g_b), "the two directions of a bond disagree"
+    past = kr > s0b * (1 + rel)
+    below = kr < s0b * (1 - rel)
+    edge = ~(past | below)
+    err = np.abs(g_a[past] - kr[past]) / kr[past]
+    print(f"damaged bonds {past.sum()}, max rel kappa error {err.max() if err.size else 0:.2e}, "
+          f"near the limit {edge.sum()}")
+    assert np.all(err <= rel)
+    assert np.all(g_a[below] == 0)
+    assert np.all((g_a[edge] == 0) | (np.abs(g_a[edge] - kr[edge]) <= rel * kr[edge]))
+    # nothing outside the oracle's bonds: the other slots hold no history
+    mask = np.zeros_like(kappa_gpu, dtype=bool)
+    mask[ka, prob.bond_i] = True
+    mask[kb, prob.bond_j] = True
+    assert np.all(kappa_gpu[~mask] == 0)
+    return int(past.sum())
 
 
 def random_fields(M, seed):
@@ -180,9 +236,30 @@ def test_fracture_run_matches_oracle(B, fracture_refs, law_idx, precision):
     # elastic phase (first quarter of the run) tracks the oracle's reaction
     q = lv.n_steps // 4
     assert rel_l2(out["R"][:q], ref["R"][:q]) < (1e-9 if precision == "f64" else 2e-5)
-    # damage history: every damaged bond direction of the oracle is damaged on the GPU
-    damaged_ref = np.sum(ref["kappa"] > 0.5 * (W.S0_MEAN + W.S0_MEAN))
-    assert np.sum(out["kappa"] > W.S0_MEAN) == pytest.approx(2 * damaged_ref, rel=0.05)
+    prob = S.beam_problem(lv)
+    if precision == "f64":
+        assert check_kappa_per_bond(out["kappa"], ref, prob, 1e-9) > 1000
+    else:
+        # FP32 trajectories leave the oracle's by rounding: the damaged-bond
+        # sets agree up to bonds near their limit
+        ka, _ = bond_slots(prob)
+        dam_gpu = out["kappa"][ka, prob.bond_i] > 0
+        dam_ref = ref["kappa"] > W.S0_MEAN
+        assert np.sum(dam_gpu != dam_ref) <= 0.02 * dam_ref.sum()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_damage_history_never_decreases(B, precision):
+    """Two recorded states of the same cracking run (deterministic: the
+    second run repeats the first one's steps bit for bit): no bond direction's
+    largest stretch decreases between step 1800 and step 2600, and some grow."""
+    lv = W.level(0, fracture=True)
+    mesh = B.Mesh.for_level(lv)
+    k1 = B.run(mesh, B.make_params(lv, precision=precision, n_steps=1800), want_state=True)["kappa"]
+    k2 = B.run(mesh, B.make_params(lv, precision=precision, n_steps=2600), want_state=True)["kappa"]
+    assert np.count_nonzero(k1) > 0
+    assert np.all(k2 >= k1)
+    assert np.count_nonzero(k2 > k1) > 0
 
 
 def test_batch_equals_single_runs(B, torch):
@@ -258,6 +335,38 @@ def test_batched_fp32_level1_full_size_matches_oracle(B, torch):
         assert abs(ns[k].item() - ref["nstar"]) <= 0.02 * lv.n_steps
 
 
+@pytest.mark.slow
+def test_headline_batch_matches_oracle_displacements(B, torch):
+    """The benchmarked workload itself: the level-1 batch of 64 lognormal-field
+    samples (seed 1), literal load, 8000 steps, FP32 with compensated
+    accumulation, in the launch configuration the benchmark times.  Samples 0
+    and 63 are re-run by the oracle on the same KL coefficients: the final
+    displacement field (elastic throughout) to relative L2 <= 1e-5 and the
+    peak (the last step's reaction) to 0.5%."""
+    lv = W.level(1)
+    mesh = B.Mesh.for_level(lv)
+    kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    xi = W.kl_coefficients(1, 64)
+    s0 = kl.lognormal(torch.tensor(xi), W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
+    Q, ns, st, u = B.run_batch([B.BatchItem(mesh, B.make_params(lv), 64, s0, want_u=True)])[0]
+    assert torch.all(st == 0)
+    u = u.cpu().numpy()
+    ob = OKL.Basis3D((lv.beam.length, lv.beam.thickness, lv.beam.depth), W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    pos = G.node_positions(mesh.shape, lv.dx)
+    picks = [0, 63]
+    probs = [S.beam_problem(lv, s0=OKL.lognormal_field(ob, pos, xi[k:k + 1], W.S0_MEAN, W.FIELD_COV)[0])
+             for k in picks]
+    refs = oracle_runs(probs, want_state=True)
+    for k, ref in zip(picks, refs):
+        e = rel_l2(u[k], ref["u"])
+        print(f"sample {k}: u rel L2 {e:.2e}, peak {Q[k].item():.6f} vs {ref['Q']:.6f}")
+        assert e <= 1e-5
+        assert Q[k].item() == pytest.approx(ref["Q"], rel=5e-3)
+        assert abs(ns[k].item() - ref["nstar"]) <= 0.02 * lv.n_steps
+        prob = probs[picks.index(k)]
+        assert np.all(ref["kappa"] <= 0.5 * (prob.s0[prob.bond_i] + prob.s0[prob.bond_j]))
+
+
 @pytest.fixture(scope="module")
 def level2_refs():
     """The level-2 mesh (140 x 40 x 40 nodes, 12.8 M bonds) for 120 steps at
@@ -288,9 +397,14 @@ def test_level2_run_matches_oracle(B, level2_refs, precision):
     assert rel_l2(out["u"], ref["u"]) < (1e-9 if precision == "f64" else 1e-4)
     live = np.abs(ref["R"]) > 1e-3 * ref["Q"]
     assert rel_l2(out["R"][live], ref["R"][live]) < (1e-9 if precision == "f64" else 1e-4)
-    damaged_ref = int(np.sum(ref["kappa"] > W.S0_MEAN))
-    assert damaged_ref > 0
-    assert np.sum(out["kappa"] > W.S0_MEAN) == pytest.approx(2 * damaged_ref, rel=1e-3 if precision == "f64" else 0.05)
+    prob = S.beam_problem(lv)
+    if precision == "f64":
+        assert check_kappa_per_bond(out["kappa"], ref, prob, 1e-9) > 0
+    else:
+        ka, _ = bond_slots(prob)
+        dam_gpu = out["kappa"][ka, prob.bond_i] > 0
+        dam_ref = ref["kappa"] > W.S0_MEAN
+        assert dam_ref.sum() > 0 and np.sum(dam_gpu != dam_ref) <= 0.02 * dam_ref.sum()
 
 
 @pytest.mark.slow

@@ -4,7 +4,6 @@ levels of Table discretisation, 350 ... 89,600 nodes) with the oracle:
 force evaluations with heterogeneous fields, cracking runs at levels 0-2 in
 FP64 and FP32, every launch shape on the one-node-thick body, and a run
 driven by the paper's material model on the plane."""
-import concurrent.futures as cf
 import dataclasses
 
 import numpy as np
@@ -108,8 +107,7 @@ def test_plane_force_eval_full_size_level4(env):
 @pytest.fixture(scope="module")
 def plane_refs():
     lvs = [W.level2d(ell) for ell in (0, 1, 2)]
-    with cf.ThreadPoolExecutor(max_workers=3) as ex:
-        refs = list(ex.map(lambda lv: S.beam_problem(lv).run(), lvs))
+    refs = S.run_many([S.beam_problem(lv) for lv in lvs])
     return list(zip(lvs, refs))
 
 
@@ -186,9 +184,7 @@ def test_plane_paper_material_run_matches_oracle(env):
     dev = lambda a: torch.tensor(a, device="cuda", dtype=torch.float32).contiguous()
     Q, ns, st = B.run_batch([B.BatchItem(m1, B.make_params(lv1), n, dev(s0), dev(c), dev(gf))])[0]
     assert torch.all(st == 0)
-    with cf.ThreadPoolExecutor(max_workers=n) as ex:
-        refs = list(ex.map(lambda k: S.beam_problem(lv1, s0=s0[k], c=c[k], gf=gf[k]).run(want_state=False),
-                           range(n)))
+    refs = S.run_many([S.beam_problem(lv1, s0=s0[k], c=c[k], gf=gf[k]) for k in range(n)], want_state=False)
     for k, ref in enumerate(refs):
         assert ref["nstar"] < lv1.n_steps
         assert Q[k].item() == pytest.approx(ref["Q"], rel=5e-3)
