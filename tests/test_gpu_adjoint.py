@@ -102,12 +102,12 @@ def batch_peaks(B, mesh, p, s0_rows, c_rows=None):
 
 @pytest.fixture(scope="module")
 def level1_fd(B):
-    """Central differences (h = 1e-4 relative) of the FP64 forward solve on 20
-    random nodes where the FP64 adjoint gradient is non-zero, for s0 and for c
-    (the micromodulus field given explicitly at its homogeneous value), and
-    along a random direction of s0.  Nodes are drawn where the relative
-    sensitivity |g_i x_i| is at least 1e-3 of its largest value, so that a
-    difference of 2e-4 |g_i x_i| stands well above the forward solve's
+    """Central differences of the FP64 forward solve on 20 random nodes where
+    the FP64 adjoint gradient is non-zero, for s0 and for c (the micromodulus
+    field given explicitly at its homogeneous value), at two steps h = 1e-4
+    and h / 4 (relative), and along a random direction of s0.  Nodes are drawn
+    where the relative sensitivity |g_i x_i| is at least 1e-3 of its largest
+    value, so that the differences stand well above the forward solve's
     rounding."""
     lv, s0 = level1_adjoint_case()
     mesh = B.Mesh.for_level(lv)
@@ -124,39 +124,52 @@ def level1_fd(B):
         live = np.nonzero(sens >= 1e-3 * sens.max())[0]
         picks = rng.choice(live, 20, replace=False)
         rows_s0, rows_c = [], []
-        for i in picks:
-            for sign in (1, -1):
-                a, b = s0.copy(), c.copy()
-                (a if name == "s0" else b)[i] *= 1 + sign * h
-                rows_s0.append(a)
-                rows_c.append(b)
+        for step in (h, h / 4):
+            for i in picks:
+                for sign in (1, -1):
+                    a, b = s0.copy(), c.copy()
+                    (a if name == "s0" else b)[i] *= 1 + sign * step
+                    rows_s0.append(a)
+                    rows_c.append(b)
         Q, ns = batch_peaks(B, mesh, p64, rows_s0, rows_c)
-        base = (s0 if name == "s0" else c)[picks]
-        out[name] = dict(picks=picks, fd=(Q[0::2] - Q[1::2]) / (2 * h * base), ns=ns)
+        base = x[picks]
+        fd_h = (Q[0:40:2] - Q[1:40:2]) / (2 * h * base)
+        fd_q = (Q[40::2] - Q[41::2]) / (2 * (h / 4) * base)
+        out["fd_" + name] = dict(picks=picks, fd=fd_q, fd_h=fd_h, ns=ns)
     dirn = rng.standard_normal(M)
     Q, _ = batch_peaks(B, mesh, p64, [s0 * (1 + h * dirn), s0 * (1 - h * dirn)], [c, c])
     out["directional"] = (dirn, (Q[0] - Q[1]) / 2)
     return out
 
 
-def fd_agreement(name, picks, fd, g, ns, nstar, rel):
-    """Per-node comparison; a node whose perturbed runs change the peak step
-    takes the gradient of another step's reaction and is reported apart."""
-    ok = 0
-    for n, (i, f) in enumerate(zip(picks, fd)):
-        flip = ns[2 * n] != nstar or ns[2 * n + 1] != nstar
-        good = abs(f - g[i]) <= rel * abs(f)
-        print(f"d/d{name} node {i}: fd {f:.6e} adjoint {g[i]:.6e} rel {abs(f - g[i]) / abs(f):.1e}"
-              f"{' (peak step moved)' if flip else ''}")
-        ok += good or flip
-    return ok
+def fd_agreement(name, f, g, nstar, rel):
+    """Per-node comparison with the central difference at h / 4.  The peak
+    load is not smooth everywhere: a perturbation that moves a bond across
+    its limit stretch at some step, or moves the peak step, changes the
+    branch the solve follows, and the difference then mixes two branches'
+    slopes, while the adjoint gives the slope of the branch taken.  Such
+    nodes show up as differences at h and h / 4 that disagree (a smooth
+    difference changes by O(h^2)); they are reported apart.  Returns
+    (nodes compared, nodes that agree)."""
+    smooth = agree = 0
+    for n, i in enumerate(f["picks"]):
+        fd, fd_h = f["fd"][n], f["fd_h"][n]
+        moved = np.any(f["ns"][[2 * n, 2 * n + 1, 40 + 2 * n, 41 + 2 * n]] != nstar)
+        ok_smooth = not moved and abs(fd_h - fd) <= 5e-3 * abs(fd)
+        good = abs(fd - g[i]) <= rel * abs(fd)
+        print(f"d/d{name} node {i}: fd(h/4) {fd:.6e} fd(h) {fd_h:.6e} adjoint {g[i]:.6e} "
+              f"rel {abs(fd - g[i]) / abs(fd):.1e}{'' if ok_smooth else ' (branch changes within h)'}")
+        smooth += ok_smooth
+        agree += ok_smooth and good
+    return smooth, agree
 
 
 @pytest.mark.slow
 def test_adjoint_level1_against_finite_differences(B, level1_fd):
     """FP64 adjoint at level 1 against central differences of the FP64
     forward solve: along a random direction of s0, and on 20 nodes each for
-    dQ/ds0 and dQ/dc drawn where the gradient is non-zero."""
+    dQ/ds0 and dQ/dc drawn where the gradient is non-zero; every node whose
+    difference is smooth agrees to 1e-2."""
     d = level1_fd
     g = d["g64"]
     dirn, fd = d["directional"]
@@ -164,15 +177,16 @@ def test_adjoint_level1_against_finite_differences(B, level1_fd):
     print(f"directional: fd {fd:.6e} adjoint {ad:.6e}")
     assert ad == pytest.approx(fd, rel=2e-2)
     for name, key in (("s0", "dQ_ds0"), ("c", "dQ_dc")):
-        ok = fd_agreement(name, d[name]["picks"], d[name]["fd"], g[key], d[name]["ns"], g["nstar"], 2e-2)
-        assert ok == 20
+        smooth, agree = fd_agreement(name, d["fd_" + name], g[key], g["nstar"], 1e-2)
+        print(f"d/d{name}: {smooth} of 20 nodes smooth, {agree} agree")
+        assert smooth >= 14 and agree == smooth
 
 
 @pytest.mark.slow
 def test_fp32_adjoint_level1_against_finite_differences(B, level1_fd):
     """The FP32 adjoint of the same workload (FP32 forward and recompute,
-    FP64 adjoint state) against the same central differences of the FP64
-    forward solve, and against the FP64 adjoint."""
+    FP64 adjoint state, checkpoints every 200 steps) against the same central
+    differences of the FP64 forward solve, and against the FP64 adjoint."""
     d = level1_fd
     g64 = d["g64"]
     p32 = B.make_params(d["lv"], precision="f32", checkpoint_every=200)
@@ -182,10 +196,11 @@ def test_fp32_adjoint_level1_against_finite_differences(B, level1_fd):
     assert g32["nstar"] == g64["nstar"]
     e0, ec = rel_l2(g32["dQ_ds0"], g64["dQ_ds0"]), rel_l2(g32["dQ_dc"], g64["dQ_dc"])
     print(f"FP32 vs FP64 adjoint rel L2: ds0 {e0:.2e}, dc {ec:.2e}")
-    assert e0 < 5e-2 and ec < 5e-2
+    assert e0 < 1e-2 and ec < 1e-2
     for name, key in (("s0", "dQ_ds0"), ("c", "dQ_dc")):
-        ok = fd_agreement(name, d[name]["picks"], d[name]["fd"], g32[key], d[name]["ns"], g64["nstar"], 1e-1)
-        assert ok >= 18
+        smooth, agree = fd_agreement(name, d["fd_" + name], g32[key], g64["nstar"], 5e-2)
+        print(f"FP32 d/d{name}: {smooth} of 20 nodes smooth, {agree} agree")
+        assert smooth >= 14 and agree >= smooth - 1
 
 
 def test_peak_load_autograd_function(B):
