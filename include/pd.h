@@ -229,6 +229,30 @@ typedef struct {
 
 PD_API int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream);
 
+/* pd_run_batch for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the same items, results bit-identical to pd_run_batch's, but every work
+ * buffer of the solve (displacement, velocity and compensation state, damage
+ * history and bits, padded fields, reaction partial sums; nstar and status
+ * when the item leaves them NULL) is carved from one 256 MiB device array
+ * that the library holds on each device it runs on until the process ends.
+ * It calls no hipMalloc, hipFree or other allocating routine and captures
+ * no graph: one step launch per item and time step on stream, items
+ * interleaved on their common clock (dt integer multiples of the finest, no
+ * lcm bound).  The launch shape is the mesh's pinned one, else the
+ * autotuner's cached choice for the configuration, else the 16x4x4 brick;
+ * it is never measured here.  Async: only enqueues on stream.  Every call
+ * on a device shares that device's array, which keeps the last call's
+ * contents (each call re-initialises what it uses): calls that overlap on
+ * one device (other streams, other host threads) race and must be
+ * serialised by the caller.  Fails with PD_EINVAL, before enqueuing
+ * anything, when the items' work buffers exceed 256 MiB (about 110
+ * level-0 samples or 15 level-1 samples of the beam), for more than 8
+ * items, or for the same argument errors as pd_run_batch; with PD_ESTATE
+ * when a mesh's tables are not on the device yet (pd_build_bonds uploads
+ * them when a device is present). */
+PD_API int pd_run_batch_static(const pd_batch_item *items, int32_t n_items, void *stream);
+
 /* Launch-shape autotuner (no paper counterpart: it only changes how the
  * work of one time step is mapped onto the GPU).  Measures every shape that
  * the configuration (mesh dims, n_samples, p->precision, p->accumulate,

@@ -135,10 +135,11 @@ class BatchItem:
     want_u: bool = False       # also return each sample's final displacement [S][M][3]
 
 
-def run_batch(items: Sequence[BatchItem], stream=None):
+def run_batch(items: Sequence[BatchItem], stream=None, no_alloc=False):
     """Returns a list of (Q, nstar, status) torch tensors, one triple per item
     (a fourth tensor, the final displacements [S][M][3], for items with
-    want_u)."""
+    want_u).  no_alloc: through pd_run_batch_static (work buffers in the
+    library's fixed device array; the outputs are still allocated here)."""
     import torch
     dev = torch.device("cuda")
     arr = (pd.pd_batch_item * len(items))()
@@ -162,7 +163,7 @@ def run_batch(items: Sequence[BatchItem], stream=None):
                                   Q.data_ptr(), ns.data_ptr(), st.data_ptr(),
                                   u.data_ptr() if u is not None else None)
         outs.append((Q, ns, st) if u is None else (Q, ns, st, u))
-    pd.pd_run_batch(arr, len(items), _stream_ptr(stream))
+    (pd.pd_run_batch_static if no_alloc else pd.pd_run_batch)(arr, len(items), _stream_ptr(stream))
     return outs
 
 

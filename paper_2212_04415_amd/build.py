@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdmi.so")
 
-SOURCES = ["geometry.cpp", "kl.cpp", "solver.hip", "fields.hip", "adjoint.hip", "material.hip",
+SOURCES = ["geometry.cpp", "kl.cpp", "solver.hip", "static_batch.hip", "fields.hip", "adjoint.hip", "material.hip",
            "launch_f32_kahan.hip", "launch_f32_kahan_c.hip", "launch_f32_plain.hip", "launch_f64.hip"]
 
 # the dense eigensolver of the exponential-covariance KL basis

@@ -158,9 +158,22 @@ struct RunBuffers {
     int32_t *status = nullptr;
     bool own_outputs = true;
     std::vector<void *> allocs;
+    // Arena mode: buffers are carved, 256-byte aligned, from a caller-given
+    // device region instead of allocated; *arena_used counts the bytes taken
+    // (shared by the solves of one call).  With a null arena only the count
+    // advances (sizing pass).
+    bool arena_mode = false;
+    char *arena = nullptr;
+    size_t *arena_used = nullptr;
 
     int alloc(void **p, size_t bytes)
     {
+        if (arena_mode) {
+            const size_t off = (*arena_used + 255) & ~(size_t)255;
+            *arena_used = off + (bytes ? bytes : 16);
+            *p = arena ? arena + off : nullptr;
+            return PD_OK;
+        }
         hipError_t e = hipMalloc(p, bytes ? bytes : 16);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(run buffers)");
         allocs.push_back(*p);

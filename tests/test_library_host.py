@@ -27,6 +27,9 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pd.SIGNATURES)
+    # and the binding has a Python function of the same name for each
+    for n in names:
+        assert callable(getattr(pd, n)), n
 
 
 def build(beam, dx, m_ratio=W.M_RATIO, extent_y=None, thickness=0.0, plane_strain=0):
