@@ -259,16 +259,23 @@ static inline bool plane_mesh(const pd_mesh_s *m) { return m->ny == 1; }
 // body one node thick (its y components stay zero), else (x, y, z).
 static inline int vel_components(const pd_mesh_s *m) { return plane_mesh(m) ? 2 : 3; }
 
+// Blocks of one step launch: one per (sample, tile) work item, padded to a
+// multiple of the XCD count.
+static int64_t step_blocks(const pd_mesh_s *m, int64_t S, const LaunchShape &sh)
+{
+    const int64_t tiles = sh.lds ? (int64_t)((m->nx + sh.bx - 1) / sh.bx) * ((m->ny + sh.by - 1) / sh.by) *
+                                       ((m->nz + sh.bz - 1) / sh.bz)
+                                 : (m->M + sh.threads - 1) / sh.threads;
+    return (tiles * S + kXcds - 1) / kXcds * kXcds;
+}
+
 // A step launch covers every (sample, tile) work item with one block; the
 // dispatch counts its work-items in 32 bits, so every shape the solve might
 // take (the autotuner tries them all) must stay below 2^32 work-items.
 static int check_launch_size(const pd_mesh_s *m, int64_t S)
 {
     for (const LaunchShape &sh : plane_mesh(m) ? kPlaneShapes : kShapes) {
-        const int64_t tiles = sh.lds ? (int64_t)((m->nx + sh.bx - 1) / sh.bx) * ((m->ny + sh.by - 1) / sh.by) *
-                                           ((m->nz + sh.bz - 1) / sh.bz)
-                                     : (m->M + sh.threads - 1) / sh.threads;
-        const int64_t blocks = (tiles * S + kXcds - 1) / kXcds * kXcds;
+        const int64_t blocks = step_blocks(m, S, sh);
         if (blocks * sh.threads > (int64_t)UINT32_MAX)
             return fail(PD_EINVAL, "%lld samples of this mesh exceed one launch (%lld work-items; at most 2^32 - 1)",
                         (long long)S, (long long)(blocks * sh.threads));
@@ -340,6 +347,8 @@ static StepParams<T> make_step_params(const Solve &s, int k_local)
     const int64_t nbz = (m->nz + sh.bz - 1) / sh.bz;
     a.tiles = sh.lds ? (int64_t)a.nbx * a.nby * nbz : (m->M + sh.threads - 1) / sh.threads;
     a.n_items = a.tiles * b.S;
+    a.chunk = a.nby * (int)nbz;
+    a.heavy_first = b.S % kXcds == 0;   // every XCD holds whole samples
     a.nz = m->nz;
     a.PY = m->PY;
     a.PZ = m->PZ;

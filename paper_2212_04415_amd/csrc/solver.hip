@@ -26,9 +26,9 @@ static void launch_step_impl(const Solve &s, int k_local, hipStream_t st, double
         a.L_out = L_out;
         a.force_only = 1;
     }
-    dim3 grid((unsigned)((a.n_items + kXcds - 1) / kXcds * kXcds));
     const int shape = effective_shape(s.b.f64, s.b.kahan, s.b.has_c, s.shape);
     const bool plane = plane_mesh(s.m);
+    dim3 grid((unsigned)step_blocks(s.m, s.b.S, (plane ? kPlaneShapes : kShapes)[shape]));
     if constexpr (sizeof(T) == 4) {
         if (s.b.kahan) {
             if (s.b.has_c) launch_f32_kahan_c(shape, plane, grid, st, a);

@@ -128,6 +128,8 @@ struct StepParams {
     int64_t tiles, n_items;    // tiles per sample, samples * tiles
     int nx, ny, nz, PX, PY, PZ, nsup;
     int nbx, nby;              // bricks along x and y (LDS path)
+    int chunk;                 // LDS path: bricks per x slab of one sample (nby * nbz)
+    int heavy_first;           // LDS path: mid-span x slabs of each sample first
     int force_only;
     int acc_mode;              // FP32 without compensation: the ablation run (PD_ACC_*)
     T two_d_b, two_d_g, dt, vload;  // integrator in units of dx
@@ -1046,11 +1048,31 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
     __shared__ double scratch[128];
     static_assert(BR::N <= 256, "one 128-entry exception list per wave in 1 KB");
     uint16_t *list = (uint16_t *)scratch + 128 * (threadIdx.x / 64);
+    // Each XCD takes a contiguous range of work items (sample major), so the
+    // halos its bricks share stay in its L2.  When every XCD holds whole
+    // samples (heavy_first), the bricks of a sample go in x slabs, the slabs
+    // nearest the mid-span plane (notch and load pad, where the damaged bonds
+    // and their costly exception pass are) first, so the cheapest bricks of
+    // each XCD come last.  (Decided on the host: a read of device state here
+    // would delay every block's start.)
     const int64_t per_xcd = gridDim.x / kXcds;
     const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
     if (item >= a.n_items) return;
     const int sample = (int)(item / a.tiles);
-    const int64_t t = item % a.tiles;
+    int64_t t = item % a.tiles;
+    if (LDS && a.heavy_first) {
+        const int sr = (int)(t / a.chunk);    // slab rank, then the brick within the slab
+        const int m = (a.nx / 2) / BR::BX;
+        int bx = m;
+        for (int q = 1, r = 0; r < sr; ++q) {   // ranks m, m - 1, m + 1, m - 2, ...
+            const int cand = (q & 1) ? m - (q + 1) / 2 : m + q / 2;
+            if (cand >= 0 && cand < a.nbx) {
+                bx = cand;
+                ++r;
+            }
+        }
+        t = bx + (int64_t)a.nbx * (t % a.chunk);
+    }
     const int64_t n = a.step_base[sample] + a.k_local;
     if (!a.force_only && t == 0 && n >= 1 && n <= a.n_steps) reduce_previous<T, BR::N>(a, sample, n, scratch);
     if (!a.force_only && n >= a.n_steps) return;   // whole block: finished sample
