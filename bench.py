@@ -13,8 +13,10 @@ resident in device memory.
 
 value = unique bond updates per second (bonds x time steps x samples / s).
 Alongside: samples/s, the plain per-sample FP64 solve of the same beam, the
-cracking-load variant, the step kernel's roofline, and the FP64 CPU oracle on
-a bounded sample of the same workload.
+cracking-load variant, the three-level MLMC hierarchy (MLMC samples/s), the
+step kernel's roofline (algorithmic bytes against the HBM peak, beside the
+counter-measured traffic), and the FP64 CPU oracle on a bounded sample of the
+same workload, on one host thread and on all of them.
 """
 from __future__ import annotations
 
@@ -28,20 +30,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic floating-point operations per bond direction of the FP32 path:
+# Roofline of the step kernel (the hot path is bound by HBM bandwidth: no
+# dense contraction, ~40 flop per ~8 algorithmic bytes).  Algorithmic bytes
+# per unique bond-update of the batched FP32 path: the bond's history word
+# (4 B), its neighbour identity shared by the samples of a mesh, and the node
+# state (u, v, their compensation terms, two fields: ~104 B per node-step)
+# amortised over the 46-57 bonds of a node: 7.8 B.
+ALG_BYTES_PER_BOND_UPDATE_F32 = 7.8
+PEAK_HBM_GBPS = 8000.0
+# Algorithmic floating-point operations per bond direction of the FP32 path
+# (a labelled extra beside the HBM roofline):
 # e = u_j - u_i (3), v.e (5), e.e (5), 2 v.e + e.e (2), |v|^2 + num (1),
 # |y| = y2 rsqrt(y2) (2), |v|(|y| + |v|) (2), s = num / den (1),
 # w = s / |y| (1), existence weight (1), y = v + e (3), G += w y (6),
 # compensated accumulation of the pair sums (12 per pair = 6 per direction).
 FLOPS_PER_BOND_DIR_F32 = 38
-FLOPS_PER_BOND_DIR_F64 = 32          # no compensation
 # Vector FP32 peak of the chip: 256 CUs x 4 SIMDs x 32 lanes x 2 (FMA) x
-# 2.4 GHz = 157.3 TFLOP/s.  The step kernel issues no packed FP32
-# instructions; its measured VALU instruction rate (SQ_INSTS_VALU over the
-# kernel time) exceeds what 16 lanes per SIMD per clock could deliver, so the
-# unpacked instructions run at the full 32-lane rate and this is the bound.
+# 2.4 GHz = 157.3 TFLOP/s.
 PEAK_TFLOPS_F32 = 256 * 4 * 32 * 2 * 2.4e9 / 1e12
-PEAK_TFLOPS_F64 = 78.6
 # step-kernel instantiation per launch shape (FP32, compensated, no c field)
 SHAPE_NAMES = ["lds 16x4x4", "lds 8x8x4", "lds 8x4x4", "global 256"]
 SHAPE_KERNELS = ["step_kernel<float, true, false, true, Brick<16, 4, 4, 2>>",
@@ -72,9 +78,34 @@ def traffic_from_profiles(kernel):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(seconds_target=15.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_threads():
+    """Threads the oracle may use: OMP_NUM_THREADS if set, else the CPUs this
+    process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.strip().isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(seconds_each=8.0):
     """The FP64 oracle on the host: one sample of the same beam and field,
-    timed over the first n steps (about 10-30 s of work)."""
+    timed over a bounded number of its steps, once on one thread and once on
+    every host thread (its force loop runs in OpenMP over fixed bond chunks)."""
     import numpy as np
     import workloads as W
     from oracle import geometry as OG
@@ -86,18 +117,29 @@ def cpu_baseline(seconds_target=15.0):
     pos = OG.node_positions(lv.shape, lv.dx)
     xi = W.kl_coefficients(1, 1)
     s0 = OKL.lognormal_field(ob, pos, xi, W.S0_MEAN, W.FIELD_COV)[0]
-    probe = OS.beam_problem(lv, s0=s0, n_steps=20)
-    t = time.perf_counter()
-    probe.run(want_state=False)
-    per_step = (time.perf_counter() - t) / 20
-    n = max(20, int(seconds_target / per_step))
-    prob = OS.beam_problem(lv, s0=s0, n_steps=n)
-    t = time.perf_counter()
-    prob.run(want_state=False)
-    dt = time.perf_counter() - t
-    return {"value": prob.n_bonds * n / dt, "unit": "bond-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 sample of the level-1 beam (seed-1 KL field), first {n} of {lv.n_steps} steps, "
-                      f"{dt:.1f} s, single-threaded C at -O2"}
+    out = {}
+    for threads in (1, host_threads()):
+        used = OS.set_threads(threads)
+        probe = OS.beam_problem(lv, s0=s0, n_steps=10)
+        t = time.perf_counter()
+        probe.run(want_state=False)
+        per_step = (time.perf_counter() - t) / 10
+        n = max(10, int(seconds_each / per_step))
+        prob = OS.beam_problem(lv, s0=s0, n_steps=n)
+        t = time.perf_counter()
+        prob.run(want_state=False)
+        dt = time.perf_counter() - t
+        out[used] = (prob.n_bonds * n / dt, n, dt)
+    OS.set_threads(host_threads())
+    cores = max(out)
+    rate, n, dt = out[cores]
+    one_rate, one_n, one_dt = out[1]
+    return {"value": rate, "unit": "bond-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": one_rate, "steps": one_n, "seconds": one_dt},
+            "sample": f"1 sample of the level-1 beam (seed-1 KL field), first {n} of {lv.n_steps} steps on "
+                      f"{cores} threads ({dt:.1f} s) and {one_n} steps on 1 thread ({one_dt:.1f} s); "
+                      f"C at -O2, OpenMP over fixed bond chunks"}
 
 
 def mlmc_leg(fracture=True, field_model="lognormal"):
@@ -274,8 +316,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain FP64 and cracking-load legs")
-    ap.add_argument("--mlmc", action="store_true",
-                    help="also run the three-level MLMC hierarchy (1024/128/16 samples + coupled partners)")
+    ap.add_argument("--no-mlmc", action="store_true",
+                    help="skip the three-level MLMC hierarchy (1024/128/16 samples + coupled partners), "
+                         "which the default run times")
     ap.add_argument("--mlmc-paper", action="store_true",
                     help="also run the MLMC hierarchy with the paper's material model (exponential covariance, "
                          "Weibull strength, fib relations)")
@@ -352,8 +395,10 @@ def main():
     value = bond_updates * args.steps / wall
     launches = lv.n_steps * args.steps
     avg_launch_s = gpu_s / launches
+    alg_bytes_per_launch = ALG_BYTES_PER_BOND_UPDATE_F32 * mesh.n_bonds * S
+    achieved_gbps = alg_bytes_per_launch / avg_launch_s / 1e9
     flops_per_launch = 2 * mesh.n_bonds * S * FLOPS_PER_BOND_DIR_F32
-    achieved = flops_per_launch / avg_launch_s / 1e12
+    achieved_tflops = flops_per_launch / avg_launch_s / 1e12
     kernel = SHAPE_KERNELS[tune["shape"]]
     traffic = traffic_from_profiles(kernel)
 
@@ -376,13 +421,18 @@ def main():
                    "load_per_step_mm": lv.du * 1e3, "accumulation": "kahan", "reaction": "f64"},
         "samples_per_s": S * args.steps / wall,
         "time_step_us": avg_launch_s * 1e6,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS_F32, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS_F32,
-                     "traffic": traffic, "kernel": kernel,
-                     "flops_per_launch": flops_per_launch, "avg_launch_us": avg_launch_s * 1e6},
-        "hbm": None if traffic is None else {"bytes_per_launch": traffic,
-                                             "GBps": traffic / avg_launch_s / 1e9,
-                                             "frac_of_8TBps": traffic / avg_launch_s / 8e12},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved_gbps / PEAK_HBM_GBPS, "traffic": traffic, "kernel": kernel,
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "algorithmic_bytes_per_bond_update": ALG_BYTES_PER_BOND_UPDATE_F32,
+                     "algorithmic_bytes_per_launch": alg_bytes_per_launch,
+                     "bond_updates_per_launch": mesh.n_bonds * S,
+                     "measured_hbm": None if traffic is None else {
+                         "bytes_per_launch": traffic, "GBps": traffic / avg_launch_s / 1e9,
+                         "frac_of_peak": traffic / avg_launch_s / 1e9 / PEAK_HBM_GBPS},
+                     "valu_extra": {"flops_per_launch": flops_per_launch, "TFLOPs": achieved_tflops,
+                                    "peak_fp32_vector_TFLOPs": PEAK_TFLOPS_F32,
+                                    "frac": achieved_tflops / PEAK_TFLOPS_F32}},
         "launch_shape": {"chosen": SHAPE_NAMES[tune["shape"]],
                          "autotune_us_per_step": {n: float(t) for n, t in zip(SHAPE_NAMES, tune["us_per_step"])}},
     }
@@ -433,8 +483,9 @@ def main():
         print(f"[bench] {key} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
 
     print("[bench] headline done", file=sys.stderr, flush=True)
-    if args.mlmc:
+    if not args.no_mlmc:
         leg("mlmc_hierarchy", mlmc_leg, fracture=True)
+        line["mlmc_samples_per_s"] = line["mlmc_hierarchy"]["mlmc_samples_per_s"]
     if args.mlmc_paper:
         leg("mlmc_hierarchy_paper_material", mlmc_leg, fracture=True, field_model="paper")
     if args.adaptive:

@@ -34,5 +34,10 @@ def test_profile_traffic_matches_the_current_kernel_source():
     assert bench.traffic_from_profiles(other) is None
 
 
-def test_peak_is_the_vector_fp32_rate():
+def test_roofline_constants():
+    """HBM bound at the chip's 8 TB/s with 7.8 algorithmic bytes per unique
+    bond-update; the FP32 vector rate (256 CUs x 4 SIMDs x 32 lanes x FMA x
+    2.4 GHz) is kept as a labelled extra."""
+    assert bench.PEAK_HBM_GBPS == 8000.0
+    assert bench.ALG_BYTES_PER_BOND_UPDATE_F32 == 7.8
     assert abs(bench.PEAK_TFLOPS_F32 - 157.2864) < 1e-9
