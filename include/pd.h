@@ -161,10 +161,14 @@ PD_API int pd_mesh_get_pads(pd_mesh m, int32_t *support, int32_t *load);
  * (micromodulus) or PD_FIELD_GF (fracture energy, N/m; the bond's critical
  * stretch then follows from the endpoint mean of G_F, appendix A).  values: [n_samples][n_nodes] of dtype
  * PD_DTYPE_F32/F64, on the device if on_device else on the host; the library
- * copies them (async on stream when on_device).  values = NULL clears the
- * field (back to the homogeneous pd_params value).  Bond values are endpoint
- * means (s0_b = (s0_i + s0_j)/2, c_b and G_F,b likewise).  pd_qoi_grad takes
- * its s0 / c fields as arguments and uses the homogeneous G_F. */
+ * copies them on stream, checks them on the device and synchronises the
+ * stream before it returns.  PD_EINVAL, with the old field kept, if a value
+ * is not finite and positive.  A C field also sets the largest micromodulus
+ * that pd_run's stability check (PD_EUNSTABLE) compares with dt.  values =
+ * NULL clears the field (back to the homogeneous pd_params value).  Bond
+ * values are endpoint means (s0_b = (s0_i + s0_j)/2, c_b and G_F,b
+ * likewise).  pd_qoi_grad takes its s0 / c fields as arguments and uses the
+ * homogeneous G_F. */
 PD_API int pd_set_material_field(pd_mesh m, int32_t field, int64_t n_samples, const void *values,
                           int32_t on_device, int32_t dtype, void *stream);
 
@@ -185,9 +189,11 @@ PD_API int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const
  * *out receives a run handle; read it with pd_qoi / pd_run_state. */
 PD_API int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out);
 
-/* Peak reaction Q (N), its first step n* (1-based) and optionally the
- * reaction history R[n_steps] (needs record_history).  Synchronises the run's
- * stream.  Returns PD_ENONFINITE if the run went non-finite. */
+/* Peak reaction Q = max_n R^n (N; the peak load of the beam, section 4),
+ * its first step n* (1-based) and optionally the reaction history
+ * R[n_steps] (needs record_history).  Synchronises the run's stream.
+ * Returns PD_ENONFINITE if the run went non-finite and PD_EUNSTABLE if its
+ * micromodulus field exceeds what dt allows. */
 PD_API int pd_qoi(pd_run_h r, double *peak, int64_t *peak_step, double *history);
 
 /* Final displacement u (m, [n_nodes][3]) and, optionally, the damage history
@@ -207,9 +213,21 @@ PD_API int pd_free_run(pd_run_h r);
  * c (micromodulus, device or NULL), gf (fracture energy in N/m, device or
  * NULL = homogeneous p->GF); outputs qoi (device FP64 [n_samples]), nstar (device
  * int64 [n_samples], nullable), status (device int32 [n_samples], nullable;
- * PD_OK or PD_ENONFINITE), u_out (device FP64 [n_samples][n_nodes][3],
- * nullable: each sample's displacement after its last step, in metres).  Enqueued on stream and synchronised before it
- * returns (the library's work buffers are released).  All items share
+ * PD_OK, PD_ENONFINITE, or PD_EUNSTABLE for a sample whose micromodulus
+ * field exceeds what dt allows), u_out (device FP64 [n_samples][n_nodes][3],
+ * nullable: each sample's displacement after its last step, in metres).
+ * These are the independent level-l solves of one MLMC sweep (section 3,
+ * Eq. MLMC_estimator and Algorithm 1): each sample runs the explicit solve
+ * of pd_run with its own fields.
+ *
+ * Asynchronous: the call validates the items, runs set-up (and, for a mesh
+ * with no pinned or cached launch shape, the autotuner, which synchronises),
+ * enqueues the whole solve on stream and returns.  The outputs are valid,
+ * and the inputs may be released or overwritten, once the stream's work
+ * enqueued so far has completed.  Work buffers come from the stream-ordered
+ * allocator and are released in stream order; the captured graph is
+ * destroyed by a later pd_run_batch or by pd_batch_sync.  On an error the
+ * call synchronises the stream before it returns.  All items share
  * precision and accumulate.  n_samples per item: 1 to 65535, and at most as
  * many as one step launch over the mesh's tiles can hold (2^32 - 1
  * work-items for every launch shape); PD_EINVAL otherwise. */
@@ -228,6 +246,11 @@ typedef struct {
 } pd_batch_item;
 
 PD_API int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream);
+
+/* Waits for every pd_run_batch enqueued on stream and destroys their
+ * graphs.  Calling it is optional: graphs of completed batches are also
+ * destroyed by the next pd_run_batch call. */
+PD_API int pd_batch_sync(void *stream);
 
 /* pd_run_batch for callers that cannot allocate device memory (code under
  * stream capture, tight serving loops, harnesses that forbid allocation):
@@ -277,7 +300,10 @@ PD_API int pd_set_launch_shape(pd_mesh m, int32_t shape);
 /* Gradient of the peak reaction Q = R^{n*} with respect to the per-node
  * limit-stretch field s0 and micromodulus field c, by a hand-written
  * discrete adjoint of the time loop with forward checkpoints every
- * p->checkpoint_every steps.  s0_dev / c_dev: device FP64 [n_nodes]
+ * p->checkpoint_every steps.  No counterpart in the paper, which samples Q
+ * only (section 4); the forward pass is pd_run's solve, so Q and n* equal
+ * pd_run's for the same fields.  PD_EUNSTABLE if c_dev exceeds what dt
+ * allows.  s0_dev / c_dev: device FP64 [n_nodes]
  * (nullable: homogeneous values).  dq_ds0_dev, dq_dc_dev: device FP64
  * [n_nodes] outputs (either nullable).  *peak_out and *peak_step_out
  * (nullable) receive Q and n*.  Synchronous on stream. */

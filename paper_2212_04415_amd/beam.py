@@ -139,7 +139,10 @@ def run_batch(items: Sequence[BatchItem], stream=None, no_alloc=False):
     """Returns a list of (Q, nstar, status) torch tensors, one triple per item
     (a fourth tensor, the final displacements [S][M][3], for items with
     want_u).  no_alloc: through pd_run_batch_static (work buffers in the
-    library's fixed device array; the outputs are still allocated here)."""
+    library's fixed device array; the outputs are still allocated here).
+    The solve is enqueued on `stream` (default: torch's current stream) and
+    this returns without waiting; the outputs are ready, in stream order, on
+    torch's current stream (a different torch stream is joined into it)."""
     import torch
     dev = torch.device("cuda")
     arr = (pd.pd_batch_item * len(items))()
@@ -164,6 +167,13 @@ def run_batch(items: Sequence[BatchItem], stream=None, no_alloc=False):
                                   u.data_ptr() if u is not None else None)
         outs.append((Q, ns, st) if u is None else (Q, ns, st, u))
     (pd.pd_run_batch_static if no_alloc else pd.pd_run_batch)(arr, len(items), _stream_ptr(stream))
+    if isinstance(stream, torch.cuda.Stream) and stream != torch.cuda.current_stream():
+        # the tensors are in use on `stream` until it reaches this point
+        for it, o in zip(items, outs):
+            for t in (it.s0, it.c, it.gf, *o):
+                if t is not None:
+                    t.record_stream(stream)
+        torch.cuda.current_stream().wait_stream(stream)
     return outs
 
 

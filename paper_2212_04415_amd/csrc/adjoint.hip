@@ -282,7 +282,8 @@ static int qoi_grad(pd_mesh_s *m, const pd_params *p, const double *s0_dev, cons
     PD_HIP(hipMemcpyAsync(&nstar, s.b.nstar, 8, hipMemcpyDeviceToHost, st));
     PD_HIP(hipMemcpyAsync(&status, s.b.status, 4, hipMemcpyDeviceToHost, st));
     PD_HIP(hipStreamSynchronize(st));
-    if (status != PD_OK) return fail(status, "the forward run produced a non-finite reaction");
+    if (status == PD_EUNSTABLE) return fail(status, "the micromodulus field exceeds what dt allows");
+    if (status != PD_OK) return fail(status, "the forward run went non-finite");
     if (peak_out) *peak_out = Q;
     if (peak_step_out) *peak_step_out = nstar;
 

@@ -114,6 +114,7 @@ struct pd_mesh_s {
     int64_t gf_samples = 0;
 
     int shape_override = -1;   // pinned launch shape (PD_SHAPE_*), -1 = tuned
+    double c_max = 0.0;        // largest value of the micromodulus field (0: none set)
 
     int64_t padded(int i, int j, int k) const
     {

@@ -110,6 +110,43 @@ static __global__ void init_qoi_kernel(double *Q, int64_t *nstar, int32_t *statu
     }
 }
 
+// Per-sample largest value of a positive field [S][M] of type In, compared
+// with `limit`: a sample whose field exceeds it gets `code` in status (the
+// explicit step is unstable where the micromodulus exceeds the value its
+// time step allows).  One block per sample.
+template <typename In>
+__global__ void field_limit_kernel(const In *f, int64_t M, double limit, int32_t code, int32_t *status)
+{
+    __shared__ double part[256];
+    const In *x = f + (int64_t)blockIdx.x * M;
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < M; i += blockDim.x) mx = fmax(mx, (double)x[i]);
+    part[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && part[0] > limit) status[blockIdx.x] = code;
+}
+
+// FP64 copy of a device field with its largest value and a count of values
+// that are not positive and finite (flags[0]: count, flags[1]: bits of the
+// largest value; a positive double's bits order like its value).
+template <typename In>
+__global__ void field_copy_check_kernel(const In *src, int64_t n, double *dst, unsigned long long *flags)
+{
+    unsigned long long bad = 0, mx = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)src[i];
+        dst[i] = v;
+        if (!(v > 0.0) || !isfinite(v)) ++bad;
+        else mx = max(mx, (unsigned long long)__double_as_longlong(v));
+    }
+    if (bad) atomicAdd(flags, bad);
+    if (mx) atomicMax(flags + 1, mx);
+}
+
 // Final displacement of every sample of a solve as FP64 [S][M][3] in metres
 // (u in units of dx, from the padded ping-pong buffer that holds u^N).
 template <typename T>
@@ -165,6 +202,10 @@ struct RunBuffers {
     bool arena_mode = false;
     char *arena = nullptr;
     size_t *arena_used = nullptr;
+    // Stream-ordered mode: buffers come from the stream-ordered allocator on
+    // this stream and are released in stream order (no synchronisation).
+    hipStream_t ordered = nullptr;
+    bool use_ordered = false;
 
     int alloc(void **p, size_t bytes)
     {
@@ -174,14 +215,14 @@ struct RunBuffers {
             *p = arena ? arena + off : nullptr;
             return PD_OK;
         }
-        hipError_t e = hipMalloc(p, bytes ? bytes : 16);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(run buffers)");
+        hipError_t e = use_ordered ? hipMallocAsync(p, bytes ? bytes : 16, ordered) : hipMalloc(p, bytes ? bytes : 16);
+        if (e != hipSuccess) return hip_fail(e, "allocating run buffers");
         allocs.push_back(*p);
         return PD_OK;
     }
     void release()
     {
-        for (void *p : allocs) (void)hipFree(p);
+        for (void *p : allocs) (void)(use_ordered ? hipFreeAsync(p, ordered) : hipFree(p));
         allocs.clear();
     }
 };
@@ -441,6 +482,12 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
     threshold_kernel<T><<<stride_blocks(m->M * S), 256, 0, st>>>((T *)s.b.thr, (const T *)s.b.s0pad, m->P, m->M, S,
                                                               m->nx, m->ny, m->PX, (int64_t)m->PX * m->PY);
     init_qoi_kernel<<<stride_blocks(S), 256, 0, st>>>(s.b.Q, s.b.nstar, s.b.status, s.b.step, S);
+    if (c && s.n_steps > 0) {
+        // the largest micromodulus a sample may have at this time step
+        const double dtc = stability_limit(m, s.p.rho, s.mat.c_ref);
+        const double c_limit = s.mat.c_ref * (dtc / s.p.dt) * (dtc / s.p.dt);
+        field_limit_kernel<In><<<(unsigned)S, 256, 0, st>>>(c, c_stride, c_limit, PD_EUNSTABLE, s.b.status);
+    }
     PD_HIP(hipGetLastError());
     return PD_OK;
 }

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <type_traits>
 #include <cstring>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -130,30 +131,64 @@ int pd_set_material_field(pd_mesh m, int32_t field, int64_t n_samples, const voi
     if (dtype != PD_DTYPE_F32 && dtype != PD_DTYPE_F64) return fail(PD_EINVAL, "unknown dtype %d", dtype);
     double **dst = field == PD_FIELD_S0 ? &m->d_s0 : field == PD_FIELD_C ? &m->d_c : &m->d_gf;
     int64_t *cnt = field == PD_FIELD_S0 ? &m->s0_samples : field == PD_FIELD_C ? &m->c_samples : &m->gf_samples;
-    if (*dst) {
-        (void)hipFree(*dst);
+    auto clear = [&]() {
+        if (*dst) (void)hipFree(*dst);
         *dst = nullptr;
         *cnt = 0;
+        if (field == PD_FIELD_C) m->c_max = 0.0;
+    };
+    if (!values) {
+        clear();
+        return PD_OK;
     }
-    if (!values) return PD_OK;
     if (n_samples < 1) return fail(PD_EINVAL, "n_samples must be positive");
-    int64_t n = n_samples * m->M;
-    std::vector<double> host(n);
-    if (on_device) {
-        std::vector<char> raw(n * (dtype == PD_DTYPE_F64 ? 8 : 4));
-        PD_HIP(hipMemcpyAsync(raw.data(), values, raw.size(), hipMemcpyDeviceToHost, (hipStream_t)stream));
-        PD_HIP(hipStreamSynchronize((hipStream_t)stream));
-        for (int64_t i = 0; i < n; ++i)
-            host[i] = dtype == PD_DTYPE_F64 ? ((const double *)raw.data())[i] : ((const float *)raw.data())[i];
-    } else {
-        for (int64_t i = 0; i < n; ++i)
-            host[i] = dtype == PD_DTYPE_F64 ? ((const double *)values)[i] : ((const float *)values)[i];
+    int rc = ensure_device(m);
+    if (rc) return rc;
+    const int64_t n = n_samples * m->M;
+    hipStream_t st = (hipStream_t)stream;
+    // checked and converted on the device into a new buffer (host values are
+    // uploaded first); the old field is replaced only if every value passes
+    void *src = const_cast<void *>(values);
+    void *staged = nullptr;
+    double *fresh = nullptr;
+    unsigned long long flags[2] = {0, 0};
+    unsigned long long *d_flags = nullptr;
+    const size_t esz = dtype == PD_DTYPE_F64 ? 8 : 4;
+    hipError_t e = hipMalloc(&fresh, 8 * n);
+    if (e == hipSuccess) e = hipMalloc(&d_flags, sizeof(flags));
+    if (e == hipSuccess) e = hipMemcpyAsync(d_flags, flags, sizeof(flags), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !on_device) {
+        e = hipMalloc(&staged, esz * n);
+        if (e == hipSuccess) e = hipMemcpyAsync(staged, values, esz * n, hipMemcpyHostToDevice, st);
+        src = staged;
     }
-    for (int64_t i = 0; i < n; ++i)
-        if (!(host[i] > 0) || !std::isfinite(host[i])) return fail(PD_EINVAL, "field values must be positive and finite");
-    PD_HIP(hipMalloc(dst, 8 * n));
-    PD_HIP(hipMemcpy(*dst, host.data(), 8 * n, hipMemcpyHostToDevice));
+    if (e == hipSuccess) {
+        if (dtype == PD_DTYPE_F64)
+            field_copy_check_kernel<double><<<stride_blocks(n), 256, 0, st>>>((const double *)src, n, fresh, d_flags);
+        else
+            field_copy_check_kernel<float><<<stride_blocks(n), 256, 0, st>>>((const float *)src, n, fresh, d_flags);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(flags, d_flags, sizeof(flags), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (staged) (void)hipFree(staged);
+    if (d_flags) (void)hipFree(d_flags);
+    if (e != hipSuccess) {
+        if (fresh) (void)hipFree(fresh);
+        return hip_fail(e, "pd_set_material_field");
+    }
+    if (flags[0] != 0) {
+        (void)hipFree(fresh);
+        return fail(PD_EINVAL, "field values must be positive and finite (%llu are not)", flags[0]);
+    }
+    clear();
+    *dst = fresh;
     *cnt = n_samples;
+    if (field == PD_FIELD_C) {
+        double mx;
+        std::memcpy(&mx, &flags[1], sizeof(mx));
+        m->c_max = mx;
+    }
     return PD_OK;
 }
 
@@ -247,7 +282,13 @@ int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out)
     r->s.p = *p;
     r->s.n_steps = p->n_steps;
     r->stream = (hipStream_t)stream;
-    double cmax = 1.0;
+    Material mref;
+    if ((rc = material_from_params(m, p, &mref))) {
+        delete r;
+        return rc;
+    }
+    // a micromodulus field stiffens bonds up to its largest value
+    const double cmax = m->d_c ? std::max(1.0, m->c_max / mref.c_ref) : 1.0;
     if ((rc = check_params(m, p, &r->s.mat, cmax))) {
         delete r;
         return rc;
@@ -287,7 +328,8 @@ int pd_qoi(pd_run_h r, double *peak, int64_t *peak_step, double *history)
         if (!r->s.b.hist_R) return fail(PD_ESTATE, "run was started without record_history");
         PD_HIP(hipMemcpy(history, r->s.b.hist_R, 8 * r->s.n_steps, hipMemcpyDeviceToHost));
     }
-    if (status != PD_OK) return fail(status, "the run produced a non-finite reaction");
+    if (status == PD_EUNSTABLE) return fail(status, "the micromodulus field exceeds what dt allows");
+    if (status != PD_OK) return fail(status, "the run went non-finite");
     return PD_OK;
 }
 
@@ -374,10 +416,41 @@ int pd_autotune(pd_mesh m, const pd_params *p, int64_t n_samples, void *stream, 
 
 static int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
 
+// Executable graphs of batches still in flight, destroyed once the event
+// recorded after their last launch has completed.
+struct PendingGraph {
+    hipStream_t stream;
+    hipGraphExec_t exec;
+    hipEvent_t done;
+};
+
+static std::mutex g_pending_mu;
+static std::vector<PendingGraph> g_pending;
+
+// Destroys the graphs whose batches have completed; with `wait`, first
+// synchronises `stream` (every graph of that stream completes).
+static void reap_graphs(bool wait, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> g(g_pending_mu);
+    std::vector<PendingGraph> keep;
+    for (const PendingGraph &pg : g_pending) {
+        const bool mine = wait && pg.stream == stream;
+        if (mine || hipEventQuery(pg.done) == hipSuccess) {
+            if (mine) (void)hipEventSynchronize(pg.done);
+            (void)hipGraphExecDestroy(pg.exec);
+            (void)hipEventDestroy(pg.done);
+        } else {
+            keep.push_back(pg);
+        }
+    }
+    g_pending.swap(keep);
+}
+
 int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
 {
     if (!items || n_items < 1) return fail(PD_EINVAL, "empty batch");
     hipStream_t st = (hipStream_t)stream;
+    reap_graphs(false, st);
     std::vector<Solve> solves(n_items);
     double dt_min = INFINITY;
     int rc = PD_OK;
@@ -391,7 +464,8 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         if (it.field_dtype != PD_DTYPE_F32 && it.field_dtype != PD_DTYPE_F64)
             return fail(PD_EINVAL, "item %d: unknown field dtype", i);
         Material mat;
-        // the c field may stiffen bonds; the stability check uses its bound when given on the host side only
+        // a micromodulus field is checked per sample on the device (status
+        // PD_EUNSTABLE for a sample whose field exceeds what dt allows)
         if ((rc = check_params(it.mesh, it.params, &mat))) return rc;
         dt_min = std::min(dt_min, it.params->dt);
     }
@@ -416,6 +490,8 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
         s.p = *it.params;
         s.n_steps = it.params->n_steps;
         material_from_params(it.mesh, it.params, &s.mat);
+        s.b.use_ordered = true;   // released in stream order: the call does not wait for the batch
+        s.b.ordered = st;
         rc = alloc_run(it.mesh, (int)it.n_samples, f64, acc, it.c != nullptr, false, s.n_steps, s.b, false,
                        it.gf != nullptr);
         if (rc) break;
@@ -499,11 +575,37 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
     }
     for (int i = 0; !rc && i < n_items; ++i)
         if (items[i].u_out) launch_export_u(solves[i], items[i].u_out, st);
-    hipError_t e = hipStreamSynchronize(st);
-    if (!rc && e != hipSuccess) rc = hip_fail(e, "batch");
-    if (exec) (void)hipGraphExecDestroy(exec);
+    if (!rc) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "batch");
+    }
+    // buffers go back in stream order; the graph is destroyed once its last
+    // launch has completed (on a later call or in pd_batch_sync)
     for (auto &s : solves) s.b.release();
+    if (exec) {
+        hipEvent_t done = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(done, st);
+        if (e == hipSuccess) {
+            std::lock_guard<std::mutex> g(g_pending_mu);
+            g_pending.push_back(PendingGraph{st, exec, done});
+        } else {
+            (void)hipStreamSynchronize(st);
+            (void)hipGraphExecDestroy(exec);
+            if (done) (void)hipEventDestroy(done);
+            if (!rc) rc = hip_fail(e, "batch completion event");
+        }
+    }
+    if (rc) (void)hipStreamSynchronize(st);
     return rc;
+}
+
+int pd_batch_sync(void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    PD_HIP(hipStreamSynchronize(st));
+    reap_graphs(true, st);
+    return PD_OK;
 }
 
 }  // extern "C"

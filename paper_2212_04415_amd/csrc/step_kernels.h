@@ -861,7 +861,7 @@ __device__ __forceinline__ void reduce_previous(const StepParams<T> &a, int samp
     }
     if (threadIdx.x == 0) {
         double R = -a.Rscale * part[0];
-        if (!isfinite(R)) a.status[sample] = PD_ENONFINITE;
+        if (!isfinite(R) && a.status[sample] == PD_OK) a.status[sample] = PD_ENONFINITE;
         if (R > a.Q[sample]) {
             a.Q[sample] = R;
             a.nstar[sample] = prev + 1;
@@ -996,6 +996,13 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
             (double)acc.z - (KF ? (double)acc.cz : 0.0);
     }
     un.w = dirty ? T(-1) : T(1);
+    // every 64 steps (and at the last): a node whose state left the finite
+    // numbers marks its sample (the reaction alone misses nodes away from
+    // the supports); a status set earlier (an unstable field) is kept
+    if (((n & 63) == 63 || n + 1 == a.n_steps) &&
+        !(isfinite(un.x) && isfinite(un.y) && isfinite(un.z) && isfinite(vh.x) && isfinite(vh.y) && isfinite(vh.z)) &&
+        a.status[sample] == PD_OK)
+        a.status[sample] = PD_ENONFINITE;
     a.u_next[(int64_t)sample * a.P + p] = un;
     store3(a.vh, vh);
     if constexpr (KS) {

@@ -77,6 +77,7 @@ SIGNATURES = {
     "pd_free_run": [_vp],
     "pd_run_batch": [_P(pd_batch_item), _i32, _vp],
     "pd_run_batch_static": [_P(pd_batch_item), _i32, _vp],
+    "pd_batch_sync": [_vp],
     "pd_autotune": [_vp, _P(pd_params), _i64, _vp, _P(_i32), _vp],
     "pd_set_launch_shape": [_vp, _i32],
     "pd_qoi_grad": [_vp, _P(pd_params), _vp, _vp, _vp, _vp, _P(_d), _P(_i64), _vp],
@@ -144,6 +145,7 @@ pd_run_state = _wrap("pd_run_state")
 pd_free_run = _wrap("pd_free_run")
 pd_run_batch = _wrap("pd_run_batch")
 pd_run_batch_static = _wrap("pd_run_batch_static")
+pd_batch_sync = _wrap("pd_batch_sync")
 pd_autotune = _wrap("pd_autotune")
 pd_set_launch_shape = _wrap("pd_set_launch_shape")
 pd_qoi_grad = _wrap("pd_qoi_grad")
