@@ -219,6 +219,58 @@ def sweep_leg(steps=1000):
     return out
 
 
+def size_effect_leg(sizes=(50, 100, 200, 400), samples=32):
+    """The statistical size-effect sweep to full length: geometrically similar
+    notched beams of depth D = 50 / 100 / 200 / 400 mm (span 3 D, length
+    3.5 D, thickness 50 mm, notch 0.2 D, dx = 2.5 mm), the cracking load at the
+    level-1 rate for 8000 D / 50 steps (the load-pad displacement at the end
+    grows with D), 32 lognormal-field samples per size (seed 4, stream = size
+    index), batched FP32.  Per size: the mean and coefficient of variation of
+    the nominal strength sigma_N = 3 P S / (2 b D^2) (the modulus of rupture of
+    the peak load P; S span, b thickness).  The largest beam runs its samples
+    in groups of 8 (bit-identical per sample), each group a progress line."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2212_04415_amd import beam as B
+    sweep = [c for c in W.configs(fracture=True) if c.name == "size_sweep"][0]
+    out = []
+    for i, lv in enumerate(sweep.levels):
+        D_mm = round(lv.beam.depth * 1e3)
+        if D_mm not in sizes:
+            continue
+        mesh = B.Mesh.for_level(lv)
+        kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+        xi = torch.tensor(W.kl_coefficients(sweep.seed, samples, stream=i))
+        group = samples if D_mm <= 200 else 8
+        Q, ns, wall = [], [], 0.0
+        for g0 in range(0, samples, group):
+            s0 = kl.lognormal(xi[g0:g0 + group], W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            q, n, st = B.run_batch([B.BatchItem(mesh, B.make_params(lv), group, s0)])[0]
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t
+            assert int(st.abs().sum()) == 0
+            Q.append(q.cpu().numpy())
+            ns.append(n.cpu().numpy())
+            print(f"[bench] size effect D = {D_mm} mm: samples {g0}..{g0 + group - 1} done ({wall:.1f} s)",
+                  file=sys.stderr, flush=True)
+            del s0
+        Q, ns = np.concatenate(Q), np.concatenate(ns)
+        b, D, S = lv.beam.thickness, lv.beam.depth, lv.beam.span
+        sig = 3.0 * Q * S / (2.0 * b * D * D) / 1e6
+        out.append({"depth_mm": D_mm, "nodes": mesh.n_nodes, "bonds": mesh.n_bonds, "samples": samples,
+                    "time_steps": lv.n_steps, "load_per_step_mm": lv.du * 1e3, "wall_s": wall,
+                    "bond_updates_per_s": mesh.n_bonds * lv.n_steps * samples / wall,
+                    "peak_load_mean_N": float(Q.mean()),
+                    "sigma_N_mean_MPa": float(sig.mean()), "sigma_N_cov": float(sig.std(ddof=1) / sig.mean()),
+                    "peak_step_mean": float(ns.mean()), "peak_step_min": int(ns.min()), "peak_step_max": int(ns.max())})
+        del kl, mesh
+        torch.cuda.empty_cache()
+    return out
+
+
 def plane_leg(samples=(2152, 567, 204, 67, 18), notched=True, eps_s=10.0):
     """The paper's own case: the plane-stress Specimen 3 (350 x 100 mm,
     t = 50 mm, half-notched) on the five levels of its Table discretisation
@@ -326,6 +378,10 @@ def main():
                     help="also run the adaptive MLMC algorithm on the three levels (RMSE target 80 N)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the size-sweep beams (D = 50..400 mm, 32 samples, first 1000 steps)")
+    ap.add_argument("--size-effect", action="store_true",
+                    help="also run the size-effect sweep to full length (D = 50..400 mm, cracking load, 32 samples "
+                         "each; about 10 minutes) and report the mean and CoV of the nominal strength per size")
+    ap.add_argument("--sizes", default="50,100,200,400", help="depths (mm) of the size-effect sweep")
     ap.add_argument("--plane", action="store_true",
                     help="also run the plane-stress Specimen-3 MLMC hierarchy (five levels, paper material model)")
     ap.add_argument("--plane-unnotched", action="store_true",
@@ -492,6 +548,8 @@ def main():
         leg("mlmc_adaptive", adaptive_leg)
     if args.sweep:
         leg("size_sweep", sweep_leg)
+    if args.size_effect:
+        leg("size_effect", size_effect_leg, sizes=tuple(int(x) for x in args.sizes.split(",")))
     if args.plane:
         leg("plane_stress_mlmc", plane_leg)
     if args.plane_unnotched:

@@ -108,3 +108,31 @@ def test_size_sweep_force_at_full_size(B, D):
             assert err <= 64 * EPS32 * sig, (D, smp, int(node), err, sig)
     print(f"D = {D} mm: {len(nodes)} nodes x 2 samples, {damaged} bonds past s0, max err / bound = {worst:.3f}")
     assert damaged > 0
+
+
+@pytest.mark.slow
+def test_size_effect_beam_full_length_matches_oracle():
+    """The D = 50 mm beam of the size-effect sweep to full length in the
+    sweep's launch configuration (32 samples, seed 4, cracking load, 8000
+    steps, FP32 with compensation): sample 0's peak load and peak step
+    against the oracle on the same KL coefficients."""
+    import torch
+    from oracle import kl as OKL
+    from paper_2212_04415_amd import beam as B
+    lv = [lv for lv in [c for c in W.configs(fracture=True) if c.name == "size_sweep"][0].levels
+          if abs(lv.beam.depth - 50e-3) < 1e-9][0]
+    mesh = B.Mesh.for_level(lv)
+    kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    xi = W.kl_coefficients(4, 32, stream=0)
+    s0 = kl.lognormal(torch.tensor(xi), W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
+    (Q, ns, st), = B.run_batch([B.BatchItem(mesh, B.make_params(lv), 32, s0)])
+    assert torch.all(st == 0)
+    ob = OKL.Basis3D((lv.beam.length, lv.beam.thickness, lv.beam.depth), W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    pos = G.node_positions(mesh.shape, lv.dx)
+    ref = S.beam_problem(lv, s0=OKL.lognormal_field(ob, pos, xi[:1], W.S0_MEAN, W.FIELD_COV)[0]).run(
+        want_state=False)
+    print(f"D = 50 mm sample 0: peak {Q[0].item():.4f} N at step {ns[0].item()}, oracle {ref['Q']:.4f} N at "
+          f"step {ref['nstar']}")
+    assert 0.1 * lv.n_steps < ref["nstar"] < lv.n_steps
+    assert Q[0].item() == pytest.approx(ref["Q"], rel=5e-3)
+    assert abs(ns[0].item() - ref["nstar"]) <= 0.02 * lv.n_steps
