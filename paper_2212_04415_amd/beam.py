@@ -75,19 +75,30 @@ class Mesh:
 def make_params(level=None, *, precision="f32", accumulate="kahan", E=None, rho=None, GF=None, s0=None,
                 k=None, alpha=None, law=None, damping=None, dt=None, du=None, n_steps=None,
                 record_history=False, checkpoint_every=0) -> pd.pd_params:
-    import workloads as W
+    """pd_params from a level description (any object with dt, du, n_steps,
+    law and a `material` record with E, rho, GF, s0, k, alpha, damping);
+    keyword values override it.  Without a level every value must be given."""
+    mat = getattr(level, "material", None)
+
+    def pick(name, value, src):
+        if value is not None:
+            return value
+        if src is None:
+            raise ValueError(f"make_params: no value for {name} (pass it or a level that carries it)")
+        return getattr(src, name)
+
     p = pd.pd_params()
-    p.E = W.E_MODULUS if E is None else E
-    p.rho = W.DENSITY if rho is None else rho
-    p.GF = W.FRACTURE_ENERGY if GF is None else GF
-    p.s0 = W.S0_MEAN if s0 is None else s0
-    p.k = W.SOFT_K if k is None else k
-    p.alpha = W.SOFT_ALPHA if alpha is None else alpha
-    p.law = (level.law if level is not None else W.LAW_TRILINEAR) if law is None else law
-    p.damping = W.DAMPING if damping is None else damping
-    p.dt = level.dt if dt is None else dt
-    p.du = level.du if du is None else du
-    p.n_steps = level.n_steps if n_steps is None else n_steps
+    p.E = pick("E", E, mat)
+    p.rho = pick("rho", rho, mat)
+    p.GF = pick("GF", GF, mat)
+    p.s0 = pick("s0", s0, mat)
+    p.k = pick("k", k, mat)
+    p.alpha = pick("alpha", alpha, mat)
+    p.damping = pick("damping", damping, mat)
+    p.law = law if law is not None else getattr(level, "law", pd.PD_LAW_TRILINEAR)
+    p.dt = pick("dt", dt, level)
+    p.du = pick("du", du, level)
+    p.n_steps = pick("n_steps", n_steps, level)
     p.precision = {"f32": pd.PD_FP32, "f64": pd.PD_FP64}[precision]
     p.accumulate = {"kahan": pd.PD_ACC_KAHAN, "plain": pd.PD_ACC_PLAIN, "state_only": pd.PD_ACC_STATE_ONLY,
                     "forces_only": pd.PD_ACC_FORCES_ONLY}[accumulate]

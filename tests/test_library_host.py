@@ -186,3 +186,30 @@ def test_force_eval_sample_count_is_bounded():
             assert "n_samples" in pd.pd_last_error()
     finally:
         pd.lib().pd_free_mesh(h)
+
+
+def test_params_come_from_the_level_description():
+    """make_params takes the material from the level it is given (the
+    binding imports no workload module) and refuses to guess without one."""
+    import ast
+    import dataclasses
+    from paper_2212_04415_amd import beam as B
+    lv = W.level(1, fracture=True)
+    p = B.make_params(lv, precision="f64")
+    assert (p.E, p.rho, p.GF, p.s0, p.k, p.alpha, p.damping) == (
+        W.E_MODULUS, W.DENSITY, W.FRACTURE_ENERGY, W.S0_MEAN, W.SOFT_K, W.SOFT_ALPHA, W.DAMPING)
+    assert (p.dt, p.du, p.n_steps, p.law, p.precision) == (lv.dt, lv.du, lv.n_steps, lv.law, pd.PD_FP64)
+    soft = dataclasses.replace(lv, material=dataclasses.replace(lv.material, E=30e9, damping=0.0))
+    q = B.make_params(soft, GF=100.0)
+    assert (q.E, q.damping, q.GF) == (30e9, 0.0, 100.0)
+    with pytest.raises(ValueError, match="no value for E"):
+        B.make_params(None, dt=1e-6, du=1e-9, n_steps=3)
+    pkg = os.path.join(os.path.dirname(pd.__file__))
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            tree = ast.parse(open(os.path.join(pkg, name)).read())
+            for node in ast.walk(tree):
+                if isinstance(node, ast.Import):
+                    assert all(a.name != "workloads" for a in node.names), name
+                if isinstance(node, ast.ImportFrom):
+                    assert node.module != "workloads", name

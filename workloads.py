@@ -51,6 +51,22 @@ DAMPING = 1.0e5             # kg m^-3 s^-1
 LAW_EXPLIN = 0              # exponential + linear softening (appendix A)
 LAW_TRILINEAR = 1           # piecewise-linear softening envelope
 
+
+@dataclass(frozen=True)
+class Material:
+    """The homogeneous material values a level carries to the solver's
+    parameter block (the constants above, as one record)."""
+    E: float = E_MODULUS
+    rho: float = DENSITY
+    GF: float = FRACTURE_ENERGY
+    s0: float = S0_MEAN
+    k: float = SOFT_K
+    alpha: float = SOFT_ALPHA
+    damping: float = DAMPING
+
+
+CONCRETE = Material()
+
 # ---------------------------------------------------------------- loading
 DT_L0 = 1.0e-6              # s at dx = 5 mm
 STEPS_L0 = 4000
@@ -93,6 +109,7 @@ class Level:
     n_steps: int
     du: float                 # prescribed load-pad displacement per step (m)
     law: int = LAW_TRILINEAR
+    material: Material = CONCRETE
 
     @property
     def shape(self):
