@@ -14,13 +14,61 @@ marshalling only."""
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
+import json
+import os
 import time
-from typing import Callable, Dict, List, Sequence, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
 from . import beam as B
 from . import pd
+
+
+class SampleFailure(RuntimeError):
+    """Samples that failed (PD_ENONFINITE / PD_EUNSTABLE) and failed again
+    when re-run; .failed lists (item, sample, status) triples."""
+
+    def __init__(self, failed):
+        super().__init__("samples failed after re-running in FP64: " +
+                         ", ".join(f"item {i} sample {k} (status {st})" for i, k, st in failed))
+        self.failed = failed
+
+
+def run_batch_requeue(items: Sequence, stream=None, run=None):
+    """B.run_batch with per-sample failure handling.  The samples are
+    independent, so a sample whose status is not PD_OK is simply run again:
+    every failed sample of every item goes into one more batch, with its own
+    field rows and the item's parameters at FP64 precision, and its peak,
+    step and status replace the failed ones.  Returns (outs, requeued) with
+    requeued a list of (item, sample) pairs; raises SampleFailure if a
+    re-run sample fails too.  run(items, stream) defaults to B.run_batch."""
+    run = B.run_batch if run is None else run
+    outs = run(items, stream=stream)
+    bad = [(i, (o[2] != 0).nonzero().flatten()) for i, o in enumerate(outs)]
+    bad = [(i, idx) for i, idx in bad if idx.numel() > 0]
+    if not bad:
+        return outs, []
+    retry = []
+    for i, idx in bad:
+        it = items[i]
+        p = pd.pd_params()
+        C.memmove(C.byref(p), C.byref(it.params), C.sizeof(p))
+        p.precision = pd.PD_FP64
+        rows = {f: (None if getattr(it, f) is None else getattr(it, f)[idx].contiguous()) for f in ("s0", "c", "gf")}
+        retry.append(dataclasses.replace(it, params=p, n_samples=int(idx.numel()), **rows))
+    again = run(retry, stream=stream)
+    failed = []
+    for (i, idx), o in zip(bad, again):
+        for k in range(len(outs[i])):
+            outs[i][k][idx] = o[k].to(outs[i][k].dtype)
+        for j, st in zip(idx.tolist(), o[2].tolist()):
+            if st != 0:
+                failed.append((i, j, st))
+    if failed:
+        raise SampleFailure(failed)
+    return outs, [(i, j) for i, idx in bad for j in idx.tolist()]
 
 
 def coupled_batch(levels: Sequence, samples: Sequence[int], seed: int, *, precision: str = "f32",
@@ -61,12 +109,9 @@ def coupled_batch(levels: Sequence, samples: Sequence[int], seed: int, *, precis
             items.append(B.BatchItem(meshes[l], p, rows.shape[0], s0, c, gf))
     torch.cuda.synchronize()
     t = time.perf_counter()
-    outs = B.run_batch(items, stream=stream)
+    outs, requeued = run_batch_requeue(items, stream=stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
-    for Q, ns, st in outs:
-        if int(st.abs().sum()) != 0:
-            raise RuntimeError("a sample went non-finite")
     Ys, sums = [], []
     for l in range(L):
         qf = outs[l][0][: samples[l]]
@@ -78,7 +123,7 @@ def coupled_batch(levels: Sequence, samples: Sequence[int], seed: int, *, precis
                 sums=[s.cpu().numpy() for s in sums], estimate=est["estimate"],
                 sampling_variance=est["sampling_variance"], levels=est["levels"], wall_s=wall,
                 bonds=[m.n_bonds for m in meshes], nodes=[m.n_nodes for m in meshes],
-                solves=[o[0].numel() for o in outs], steps=[lv.n_steps for lv in levels])
+                solves=[o[0].numel() for o in outs], steps=[lv.n_steps for lv in levels], requeued=requeued)
 
 
 # ---------------------------------------------------------------- adaptive MLMC
@@ -148,20 +193,23 @@ def solver_sampler(levels: Sequence, seed: int, *, precision: str = "f32", corr_
             if l > 0:
                 items.append(item(l - 1, xi, count))
                 owners.append((l, "coarse"))
-        outs = B.run_batch(items, stream=stream)
+        outs, requeued = run_batch_requeue(items, stream=stream)
+        for i, j in requeued:
+            l, kind = owners[i]
+            run.requeued.append((l, kind, requests[l][0] + j))
         res: Dict[int, list] = {}
         for (l, kind), (Q, ns, st) in zip(owners, outs):
-            if int(st.abs().sum()) != 0:
-                raise RuntimeError(f"level {l}: a sample went non-finite")
             res.setdefault(l, [None, None])[0 if kind == "fine" else 1] = Q
         return {l: (v[0], v[1]) for l, v in res.items()}
+
+    run.requeued = []    # (level, "fine" | "coarse", sample index) of every re-run sample
 
     return run, costs, dofs
 
 
 def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[float], *, n_warm: int = 100,
              alpha=None, alpha_default: float = 0.5, refinement: float = 8.0, r: float = 1.0, max_levels=None,
-             stream=None):
+             stream=None, journal: Optional[str] = None, journal_tag=None):
     """Adaptive MLMC, Algorithm 1.  run({level: (start, count)}) returns
     {level: (q_fine, q_coarse or None)} device FP64 tensors (see
     solver_sampler); costs[l] is the cost of one level-l sample and dofs[l]
@@ -173,7 +221,15 @@ def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[f
     down), the additional samples of every level in one run() call, and the
     bias estimate of the finest level, with alpha fitted from |Y_hat_l|,
     l >= 1, when alpha is None and two such levels exist.  Stops when the
-    bias estimate is below eps_b, or at the last level (converged False)."""
+    bias estimate is below eps_b, or at the last level (converged False).
+
+    journal: path of an append-only JSONL record of every sample (a header
+    with journal_tag, costs, dofs, eps and n_warm, then one line per sample:
+    level, index, Q_f, Q_c, cost).  Samples already in it are read back
+    instead of being run, so a run restarted after an interruption replays
+    the same decisions and ends with the same level sums and estimate,
+    bit for bit, running only the samples the journal lacks.  A journal
+    written for another configuration is refused."""
     import torch
     eps_s = eps_b = eps / np.sqrt(2.0)
     last = len(costs) - 1 if max_levels is None else max_levels - 1
@@ -181,16 +237,50 @@ def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[f
     sums: List[np.ndarray] = []
     history = []
     wall = 0.0
+    header = dict(kind="header", tag=journal_tag, costs=[float(c) for c in costs], dofs=[float(d) for d in dofs],
+                  eps=float(eps), n_warm=int(n_warm))
+    known = _read_journal(journal, header) if journal else {}
+    sink = open(journal, "a") if journal else None
+    if sink is not None and not known and sink.tell() == 0:
+        _append(sink, [header])
+    replayed = 0
 
     def take(requests):
-        nonlocal wall
+        nonlocal wall, replayed
         torch.cuda.synchronize()
         t = time.perf_counter()
-        got = run({l: (N[l], c) for l, c in requests.items()})
-        for l, (qf, qc) in got.items():
+        # per level: the journal's prefix of the requested range, the rest run
+        first = {}
+        for l, c in requests.items():
+            k = 0
+            while k < c and (l, N[l] + k) in known:
+                k += 1
+            first[l] = k
+        todo = {l: (N[l] + first[l], c - first[l]) for l, c in requests.items() if first[l] < c}
+        got = run(todo) if todo else {}
+        records = []
+        for l, c in requests.items():
+            old = [known[(l, N[l] + k)] for k in range(first[l])]
+            replayed += len(old)
+            qf = torch.tensor([r[0] for r in old], dtype=torch.float64, device="cuda")
+            qc = torch.tensor([r[1] for r in old], dtype=torch.float64, device="cuda") if l > 0 else None
+            if l in got:
+                nf, nc = got[l]
+                qf = torch.cat([qf, nf.to(torch.float64)])
+                if l > 0:
+                    qc = torch.cat([qc, nc.to(torch.float64)])
+                hf = nf.cpu().tolist()
+                hc = nc.cpu().tolist() if l > 0 else [None] * len(hf)
+                for k, (a, b) in enumerate(zip(hf, hc)):
+                    i = N[l] + first[l] + k
+                    if (l, i) not in known:
+                        known[(l, i)] = (a, b)
+                        records.append(dict(level=l, i=i, q_f=a, q_c=b, cost=float(costs[l])))
             s = B.level_stats(qf.contiguous(), None if qc is None else qc.contiguous(), stream=stream)
             sums[l] += s.cpu().numpy()
-            N[l] += requests[l]
+            N[l] += c
+        if sink is not None and records:
+            _append(sink, records)
         torch.cuda.synchronize()
         wall += time.perf_counter() - t
 
@@ -229,10 +319,53 @@ def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[f
             break
         L += 1
     est = moments()
+    if sink is not None:
+        sink.close()
     return dict(L=L, N=N, sums=[tuple(x) for x in sums], estimate=est["estimate"],
                 sampling_variance=est["sampling_variance"], levels=est["levels"], bias=history[-1]["bias"],
                 converged=converged, history=history, eps_s=eps_s, eps_b=eps_b, wall_s=wall,
-                cost=float(sum(n * c for n, c in zip(N, costs))))
+                cost=float(sum(n * c for n, c in zip(N, costs))), replayed=replayed)
+
+
+def _append(f, records):
+    """Appends JSON lines and forces them to disk (a record is either
+    whole in the file or absent, up to a torn last line)."""
+    f.write("".join(json.dumps(r) + "\n" for r in records))
+    f.flush()
+    os.fsync(f.fileno())
+
+
+def _read_journal(path, header):
+    """{(level, index): (q_f, q_c)} from a journal; a torn last line (an
+    interrupted write) is dropped and cut from the file so that appends
+    start on a fresh line.  Raises ValueError if the header differs."""
+    if not os.path.exists(path):
+        return {}
+    with open(path, "rb") as f:
+        data = f.read()
+    lines = data.split(b"\n")
+    keep = len(data)
+    if lines[-1] != b"":          # no newline after the last line: torn
+        keep -= len(lines[-1])
+    lines = lines[:-1]
+    out = {}
+    for n, raw in enumerate(lines):
+        try:
+            rec = json.loads(raw)
+        except ValueError:
+            if n == len(lines) - 1:
+                keep -= len(raw) + 1
+                break
+            raise ValueError(f"{path}: line {n + 1} is not JSON")
+        if n == 0:
+            if rec != json.loads(json.dumps(header)):
+                raise ValueError(f"{path} was written for another configuration: {rec} != {header}")
+            continue
+        out[(int(rec["level"]), int(rec["i"]))] = (rec["q_f"], rec["q_c"])
+    if keep < len(data):
+        with open(path, "r+b") as f:
+            f.truncate(keep)
+    return out
 
 
 # ---------------------------------------------------------------- multilevel CDF

@@ -172,3 +172,84 @@ def test_multilevel_cdf_matches_the_oracle(sizes):
     ref_q = OM.ml_inverse_cdf(fine, coarse, u)
     assert np.array_equal(qs, ref_q)
     assert np.array_equal(cs, OM.ecdf(ref_q, x))
+
+
+def test_adaptive_resumes_from_its_journal(tmp_path):
+    """Algorithm 1 with a journal, on analytic samples: a second run on a
+    journal cut in half (with a torn last line) runs only the samples the
+    journal lacks and ends with the first run's counts, level sums and
+    estimate bit for bit; on the whole journal it runs nothing."""
+    import torch
+    from paper_2212_04415_amd import mlmc as PM
+    evaluated = []
+
+    def run(requests):
+        out = {}
+        for l, (start, count) in requests.items():
+            evaluated.append(count)
+            xi = _toy_xi(l, start, count)
+            qf = torch.tensor(_toy_q(l, xi), device="cuda")
+            qc = torch.tensor(_toy_q(l - 1, xi), device="cuda") if l > 0 else None
+            out[l] = (qf, qc)
+        return out
+
+    costs = [8.0 ** l for l in range(5)]
+    dofs = [1000.0 * 8 ** l for l in range(5)]
+    path = tmp_path / "adaptive.jsonl"
+    kw = dict(n_warm=10, alpha=None, alpha_default=0.5, journal=str(path), journal_tag={"toy": 5})
+    first = PM.adaptive(run, 20.0, costs, dofs, **kw)
+    total = sum(first["N"])
+    assert sum(evaluated) == total and first["replayed"] == 0
+    lines = path.read_text().splitlines(keepends=True)
+    assert len(lines) == 1 + total
+    half = total // 2
+    path.write_text("".join(lines[:1 + half]) + lines[1 + half][:7])
+    evaluated.clear()
+    second = PM.adaptive(run, 20.0, costs, dofs, **kw)
+    assert second["replayed"] == half and sum(evaluated) == total - half
+    assert second["N"] == first["N"] and second["L"] == first["L"]
+    assert second["sums"] == first["sums"] and second["estimate"] == first["estimate"]
+    assert len(path.read_text().splitlines()) == 1 + total
+    evaluated.clear()
+    third = PM.adaptive(run, 20.0, costs, dofs, **kw)
+    assert evaluated == [] and third["replayed"] == total and third["estimate"] == first["estimate"]
+    with pytest.raises(ValueError, match="another configuration"):
+        PM.adaptive(run, 12.0, costs, dofs, **kw)
+
+
+def test_failed_samples_are_requeued_on_the_device():
+    """run_batch_requeue on the solver: a sample whose status the first
+    batch reports as failed (set by a wrapper around the real batch) is run
+    again at FP64 from its own field row, and then equals the FP64 run of
+    that sample; a sample with a NaN micromodulus fails again and is
+    reported."""
+    import dataclasses
+    import torch
+    from paper_2212_04415_amd import beam as B
+    from paper_2212_04415_amd import mlmc as PM
+    from paper_2212_04415_amd import pd
+    lv = dataclasses.replace(W.level(0, fracture=True), n_steps=300)
+    mesh = B.Mesh.for_level(lv)
+    g = torch.Generator("cuda").manual_seed(2)
+    s0 = W.S0_MEAN * (1.0 + 0.1 * torch.randn((3, mesh.n_nodes), dtype=torch.float64, device="cuda", generator=g)).abs()
+    item = B.BatchItem(mesh, B.make_params(lv), 3, s0)
+    calls = []
+
+    def flaky(items, stream=None):
+        outs = B.run_batch(items, stream=stream)
+        calls.append([it.params.precision for it in items])
+        if len(calls) == 1:
+            outs[0][2][1] = pd.PD_ENONFINITE
+        return outs
+
+    (Q, ns, st), = PM.run_batch_requeue([item], run=flaky)[0]
+    assert calls == [[pd.PD_FP32], [pd.PD_FP64]] and torch.all(st == 0)
+    (Q64, n64, _), = B.run_batch([B.BatchItem(mesh, B.make_params(lv, precision="f64"), 1, s0[1:2].contiguous())])
+    (Q32, n32, _), = B.run_batch([item])
+    assert Q[1] == Q64[0] and ns[1] == n64[0]
+    assert Q[0] == Q32[0] and Q[2] == Q32[2]
+    c = torch.full((3, mesh.n_nodes), S.micromodulus(W.E_MODULUS, 3.14 * lv.dx), dtype=torch.float64, device="cuda")
+    c[2, mesh.n_nodes // 2] = float("nan")
+    with pytest.raises(PM.SampleFailure) as ei:
+        PM.run_batch_requeue([B.BatchItem(mesh, B.make_params(lv), 3, s0, c)])
+    assert ei.value.failed == [(0, 2, pd.PD_ENONFINITE)]
