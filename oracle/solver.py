@@ -32,6 +32,23 @@ LAW_EXPLIN = 0
 LAW_TRILINEAR = 1
 
 
+def build_sanitized(out: str) -> str:
+    """The same source built with AddressSanitizer and UBSan (-O1, frame
+    pointers kept) into `out`, for a host check of the oracle's memory
+    accesses; load it with PD_ORACLE_LIB=<out> in a process that preloads
+    sanitizer_runtime()."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", out,
+                           _SRC, "-lm"])
+    return out
+
+
+def sanitizer_runtime() -> str:
+    """gcc's AddressSanitizer runtime (to preload ahead of Python)."""
+    return subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+
+
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (-O2, no fast-math, OpenMP over the
     force loop's fixed bond chunks)."""
@@ -70,9 +87,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        L = C.CDLL(_LIB)
+        path = os.environ.get("PD_ORACLE_LIB")     # a sanitizer build of the same source
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB):
+                build(force=False)
+        L = C.CDLL(path)
         P = C.POINTER(_Problem)
         d, i64 = C.c_double, C.c_int64
         L.pdo_critical_stretch.restype = d

@@ -103,6 +103,41 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(out: str) -> str:
+    """The library with AddressSanitizer on its host code (-O1 -g) into
+    `out`, for host checks of the entry points that run without a GPU (mesh
+    and bond construction, argument checks, the MLMC allocation, bias and
+    rate fit).  The device code is compiled as usual but never run from
+    this build.  Load it with PDMI_LIB=<out> in a process that preloads
+    sanitizer_runtime()."""
+    from concurrent.futures import ThreadPoolExecutor
+    import tempfile
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
+             "-fvisibility=hidden", "-Wno-unused-result",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with tempfile.TemporaryDirectory(prefix="pdmi_asan_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in sources()]
+        cmds = [[HIPCC, *flags, *inc, "-c", "-o", o, src] for o, src in zip(objs, sources())]
+        with ThreadPoolExecutor(max_workers=min(len(cmds), 16, max(1, os.cpu_count() or 1))) as ex:
+            for f in [ex.submit(_compile, c) for c in cmds]:
+                f.result()
+        subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out, *objs, *LIBS])
+    return out
+
+
+def sanitizer_runtime() -> str:
+    """The AddressSanitizer runtime of the compiler that built the library
+    (to preload ahead of Python)."""
+    import glob
+    found = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not found:
+        raise FileNotFoundError("no clang AddressSanitizer runtime under /opt/rocm/llvm")
+    return found[-1]
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
     print(LIB)

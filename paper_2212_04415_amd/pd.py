@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpdmi.so")
+# PDMI_LIB selects another build of the same library (the sanitizer build)
+LIB_PATH = os.environ.get("PDMI_LIB") or os.path.join(HERE, "libpdmi.so")
 
 PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_EUNSTABLE, PD_ENONFINITE, PD_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PD_LAW_EXPLIN, PD_LAW_TRILINEAR = 0, 1
