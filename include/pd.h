@@ -228,7 +228,12 @@ PD_API int pd_free_run(pd_run_h r);
  * allocator and are released in stream order; the captured graph is
  * destroyed by a later pd_run_batch or by pd_batch_sync.  On an error the
  * call synchronises the stream before it returns.  All items share
- * precision and accumulate.  n_samples per item: 1 to 65535, and at most as
+ * precision and accumulate.  The environment variable
+ * PD_BATCH_SCHEDULE=tick replaces the per-item graph branches by one step
+ * launch per tick over every item that steps at that tick (FP32
+ * compensated 3D items with a common micromodulus mode, at most 4 of
+ * them; other batches keep the branches); the results are the same bit for
+ * bit.  n_samples per item: 1 to 65535, and at most as
  * many as one step launch over the mesh's tiles can hold (2^32 - 1
  * work-items for every launch shape); PD_EINVAL otherwise. */
 typedef struct {

@@ -9,4 +9,9 @@ void launch_f32_kahan_c(int shape, bool plane, dim3 grid, hipStream_t st, const 
     launch_shape<float, true, true>(shape, plane, grid, st, a);
 }
 
+void launch_tick_f32_kahan_c(int shape, dim3 grid, hipStream_t st, const TickParams<float> &m)
+{
+    launch_tick_shape<true>(shape, grid, st, m);
+}
+
 }  // namespace pdmi

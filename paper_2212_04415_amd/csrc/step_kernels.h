@@ -1045,7 +1045,7 @@ __device__ __forceinline__ void node_step_mode(const StepParams<T> &a, const Src
 // its neighbours stays in that XCD's L2.  The grid is padded to a multiple of
 // 8 and surplus blocks exit.
 template <typename T, bool KAHAN, bool HAS_C, bool LDS, typename BR>
-__global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
+__device__ __forceinline__ void step_tile(const StepParams<T> &a, int64_t item)
 {
     using V4 = typename Vec4<T>::t;
     __shared__ V4 tile[LDS ? BR::TILE : 1];
@@ -1062,9 +1062,6 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
     // and their costly exception pass are) first, so the cheapest bricks of
     // each XCD come last.  (Decided on the host: a read of device state here
     // would delay every block's start.)
-    const int64_t per_xcd = gridDim.x / kXcds;
-    const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    if (item >= a.n_items) return;
     const int sample = (int)(item / a.tiles);
     int64_t t = item % a.tiles;
     if (LDS && a.heavy_first) {
@@ -1125,6 +1122,38 @@ __global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
                                HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr, (uint32_t)p * (uint32_t)sizeof(T)};
         node_step_mode<T, KAHAN, HAS_C, BR::PLANE>(a, src, tab, sample, n, node, p, U[p], valid, list);
     }
+}
+
+template <typename T, bool KAHAN, bool HAS_C, bool LDS, typename BR>
+__global__ __launch_bounds__(BR::N) void step_kernel(StepParams<T> a)
+{
+    const int64_t per_xcd = gridDim.x / kXcds;
+    const int64_t item = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (item >= a.n_items) return;
+    step_tile<T, KAHAN, HAS_C, LDS, BR>(a, item);
+}
+
+// One time tick of several solves (the levels of a batch) in one launch: the
+// work items of solve i occupy [first[i], first[i] + p[i].n_items) of one
+// work list, which the XCDs take in contiguous ranges as above.
+constexpr int kMaxTickItems = 4;
+
+template <typename T>
+struct TickParams {
+    StepParams<T> p[kMaxTickItems];
+    int64_t first[kMaxTickItems + 1];
+    int n;
+};
+
+template <typename T, bool KAHAN, bool HAS_C, bool LDS, typename BR>
+__global__ __launch_bounds__(BR::N) void step_kernel_tick(TickParams<T> m)
+{
+    const int64_t per_xcd = gridDim.x / kXcds;
+    const int64_t g = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (g >= m.first[m.n]) return;
+    int i = 0;
+    while (i + 1 < m.n && g >= m.first[i + 1]) ++i;
+    step_tile<T, KAHAN, HAS_C, LDS, BR>(m.p[i], g - m.first[i]);
 }
 
 // Moves every sample's chunk base past the steps of one replayed chunk.

@@ -47,6 +47,19 @@ static void launch_shape(int shape, bool plane, dim3 grid, hipStream_t st, const
     }
     step_kernel<T, KAHAN, HAS_C, false, Brick<256, 1, 1>><<<grid, 256, 0, st>>>(a);
 }
+
+// The same choice for the several-solve tick kernel (FP32 compensated
+// accumulation, 3D meshes).
+template <bool HAS_C>
+static void launch_tick_shape(int shape, dim3 grid, hipStream_t st, const TickParams<float> &m)
+{
+    switch (shape) {
+    case PD_SHAPE_LDS_16x4x4: step_kernel_tick<float, true, HAS_C, true, Brick<16, 4, 4, 2>><<<grid, 256, 0, st>>>(m); return;
+    case PD_SHAPE_LDS_8x8x4: step_kernel_tick<float, true, HAS_C, true, Brick<8, 8, 4>><<<grid, 256, 0, st>>>(m); return;
+    case PD_SHAPE_LDS_8x4x4: step_kernel_tick<float, true, HAS_C, true, Brick<8, 4, 4>><<<grid, 128, 0, st>>>(m); return;
+    default: step_kernel_tick<float, true, HAS_C, false, Brick<256, 1, 1>><<<grid, 256, 0, st>>>(m); return;
+    }
+}
 #endif
 
 // plane: the mesh is one node thick (PlaneBrick instantiations)
@@ -56,5 +69,8 @@ void launch_f32_plain(int shape, bool plane, dim3 grid, hipStream_t st, const St
 void launch_f32_plain_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<float> &a);
 void launch_f64(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<double> &a);
 void launch_f64_c(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<double> &a);
+// one tick of several FP32 compensated 3D solves that share a launch shape
+void launch_tick_f32_kahan(int shape, dim3 grid, hipStream_t st, const TickParams<float> &m);
+void launch_tick_f32_kahan_c(int shape, dim3 grid, hipStream_t st, const TickParams<float> &m);
 
 }  // namespace pdmi

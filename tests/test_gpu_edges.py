@@ -79,3 +79,34 @@ def test_batch_beyond_one_launch_is_refused(env):
         B.run_batch([B.BatchItem(mesh, B.make_params(lv), 65535)])
     (Q, ns, st), = B.run_batch([B.BatchItem(mesh, B.make_params(lv), 2)])
     assert torch.all(st == 0)
+
+
+def test_tick_schedule_equals_the_branch_schedule(env, monkeypatch):
+    """A three-level batch (dt ratios 4 : 2 : 1, uneven step counts, lognormal
+    limit-stretch fields) run with one launch per tick over all levels gives
+    the graph-branch schedule's peaks, steps and final displacements bit
+    for bit; so does a pair of levels with a micromodulus field."""
+    torch, B = env
+    lvs = [dataclasses.replace(W.level(l, fracture=True), n_steps=n, du=2e-7 / 2 ** l)
+           for l, n in ((0, 90), (1, 170), (2, 333))]
+    meshes = [B.Mesh.for_level(lv) for lv in lvs]
+    g = torch.Generator("cuda").manual_seed(4)
+
+    def field(mesh, S, scale):
+        return scale * (1.0 + 0.1 * torch.randn((S, mesh.n_nodes), dtype=torch.float64, device="cuda",
+                                                generator=g)).abs()
+
+    s0 = [field(m, S, W.S0_MEAN) for m, S in zip(meshes, (5, 3, 2))]
+    items = [B.BatchItem(m, B.make_params(lv), f.shape[0], f, want_u=True) for m, lv, f in zip(meshes, lvs, s0)]
+    c = [field(m, 2, S.micromodulus(W.E_MODULUS, 3.14 * lv.dx)) for m, lv in zip(meshes[:2], lvs[:2])]
+    items_c = [B.BatchItem(m, B.make_params(lv), 2, f[:2].contiguous(), cc)
+               for m, lv, f, cc in zip(meshes[:2], lvs[:2], s0[:2], c)]
+    ref = B.run_batch(items)
+    ref_c = B.run_batch(items_c)
+    monkeypatch.setenv("PD_BATCH_SCHEDULE", "tick")
+    got = B.run_batch(items)
+    got_c = B.run_batch(items_c)
+    for a, b in zip(ref + ref_c, got + got_c):
+        assert torch.all(a[2] == 0)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
