@@ -488,11 +488,7 @@ def main():
                          "frac_of_peak": traffic / avg_launch_s / 1e9 / PEAK_HBM_GBPS},
                      "valu_extra": {"flops_per_launch": flops_per_launch, "TFLOPs": achieved_tflops,
                                     "peak_fp32_vector_TFLOPs": PEAK_TFLOPS_F32,
-                                    "frac": achieved_tflops / PEAK_TFLOPS_F32,
-                                    # the library is built without packed FP32 instructions:
-                                    # one FP32 FMA per lane per clock
-                                    "peak_unpacked_fp32_TFLOPs": PEAK_TFLOPS_F32 / 2,
-                                    "frac_unpacked": achieved_tflops / (PEAK_TFLOPS_F32 / 2)}},
+                                    "frac": achieved_tflops / PEAK_TFLOPS_F32}},
         "launch_shape": {"chosen": SHAPE_NAMES[tune["shape"]],
                          "autotune_us_per_step": {n: float(t) for n, t in zip(SHAPE_NAMES, tune["us_per_step"])}},
     }
