@@ -155,6 +155,16 @@ struct Acc3 {
             z += pz;
         }
     }
+    __device__ __forceinline__ void add_xz(T px, T pz)
+    {
+        if constexpr (KAHAN) {
+            kahan(x, cx, px);
+            kahan(z, cz, pz);
+        } else {
+            x += px;
+            z += pz;
+        }
+    }
     __device__ __forceinline__ static void kahan(T &s, T &c, T v)
     {
         T yv = v - c;
@@ -184,15 +194,23 @@ __device__ __forceinline__ T term_c(T e)
     else return T(2 * SIGN * C) + e;
 }
 
-template <typename T, int VX, int VY, int VZ, int SIGN>
+// PLANE: a body one node thick, whose y displacements are identically zero
+// and whose bonds all lie in the x-z plane (VY = 0), so the y term of num is
+// exactly zero and is left out.
+template <typename T, int VX, int VY, int VZ, int SIGN, bool PLANE = false>
 __device__ __forceinline__ T num_c(const typename Vec4<T>::t &ui, const typename Vec4<T>::t &uj, T &ex, T &ey,
                                    T &ez)
 {
+    static_assert(!PLANE || VY == 0, "in-plane offsets only");
     ex = uj.x - ui.x;
-    ey = uj.y - ui.y;
     ez = uj.z - ui.z;
     T n = ex * term_c<VX, SIGN>(ex);
-    n = fma_(ey, term_c<VY, SIGN>(ey), n);
+    if constexpr (PLANE) {
+        ey = T(0);
+    } else {
+        ey = uj.y - ui.y;
+        n = fma_(ey, term_c<VY, SIGN>(ey), n);
+    }
     return fma_(ez, term_c<VZ, SIGN>(ez), n);
 }
 
@@ -430,8 +448,8 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
         constexpr Off v = kHalf.v[K];
         constexpr int V2 = v.x * v.x + v.y * v.y + v.z * v.z;
         T eax, eay, eaz, ebx, eby, ebz, wa, wb;
-        const T na = num_c<T, v.x, v.y, v.z, 1>(ui, r.a, eax, eay, eaz);
-        const T nb = num_c<T, v.x, v.y, v.z, -1>(ui, r.b, ebx, eby, ebz);
+        const T na = num_c<T, v.x, v.y, v.z, 1, PLANE>(ui, r.a, eax, eay, eaz);
+        const T nb = num_c<T, v.x, v.y, v.z, -1, PLANE>(ui, r.b, ebx, eby, ebz);
         bool exa = false, exb = false;
         if constexpr (sizeof(T) == 4) {
             // x = h num with h = 1/(2|v|^2), and w = (x/|v|)(1 - 3/2 x + 5/2 x^2)
@@ -503,9 +521,13 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
             else return fma_(wa, ea, fma_(dw, T(C), base));
         };
         pend_x = part(std::integral_constant<int, v.x>{}, eax, ebx, pend_x);
-        pend_y = part(std::integral_constant<int, v.y>{}, eay, eby, pend_y);
+        if constexpr (!PLANE) pend_y = part(std::integral_constant<int, v.y>{}, eay, eby, pend_y);
         pend_z = part(std::integral_constant<int, v.z>{}, eaz, ebz, pend_z);
-        if constexpr (I % G == G - 1 || I + 1 == NP) acc.add(pend_x, pend_y, pend_z);
+        if constexpr (I % G == G - 1 || I + 1 == NP) {
+            // a plane body has no y force (its y sums would stay exactly zero)
+            if constexpr (PLANE) acc.add_xz(pend_x, pend_z);
+            else acc.add(pend_x, pend_y, pend_z);
+        }
     };
     // neighbours read through the caches hold more registers in flight
     constexpr int D = (sizeof(T) == 4 && Src::kLds) ? PD_PIPE_DEPTH : 2;
