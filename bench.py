@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -76,6 +77,18 @@ def traffic_from_profiles(kernel):
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != "pdmi::" + kernel:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def finite_json(x):
+    """The bench line with every non-finite float replaced by null (strict
+    JSON has no NaN or infinity)."""
+    if isinstance(x, dict):
+        return {k: finite_json(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite_json(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
 
 
 def cpu_model():
@@ -164,7 +177,7 @@ def mlmc_leg(fracture=True, field_model="lognormal"):
             "multilevel_quantiles_N": {str(k): float(v) for k, v in zip(u, quant)},
             "mlmc_samples_per_s": (1024 + 128 + 16) / out["wall_s"],
             "solves_per_level": out["solves"], "estimate_N": out["estimate"],
-            "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "sampling_std_N": max(out["sampling_variance"], 0.0) ** 0.5,
             "level_mean_var": [[m, v] for m, v, _ in out["levels"]],
             "load_per_step_mm_L0": levels[0].du * 1e3}
 
@@ -180,7 +193,7 @@ def adaptive_leg(eps=80.0, n_warm=100):
                                            kl_coefficients=W.kl_coefficients)
     out = mlmc.adaptive(run, eps, costs, dofs, n_warm=n_warm, alpha=None, alpha_default=0.5)
     return {"eps_N": eps, "levels_used": out["L"] + 1, "converged": out["converged"], "N": out["N"],
-            "estimate_N": out["estimate"], "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "estimate_N": out["estimate"], "sampling_std_N": max(out["sampling_variance"], 0.0) ** 0.5,
             "bias_estimate_N": out["bias"], "alpha_fitted": out["history"][-1]["alpha"],
             "wall_s": out["wall_s"], "bond_updates_per_s": out["cost"] / out["wall_s"],
             "mlmc_samples_per_s": sum(out["N"]) / out["wall_s"]}
@@ -306,7 +319,7 @@ def plane_leg(samples=(2152, 567, 204, 67, 18), notched=True, eps_s=10.0):
                               "mlmc_bond_updates": bu, "cost_ratio_mc_over_mlmc": mc_cost / bu},
             "steps": out["steps"], "solves_per_level": out["solves"], "wall_s": out["wall_s"],
             "bond_updates_per_s": bu / out["wall_s"], "mlmc_samples_per_s": sum(samples) / out["wall_s"],
-            "estimate_N": out["estimate"], "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "estimate_N": out["estimate"], "sampling_std_N": max(out["sampling_variance"], 0.0) ** 0.5,
             "level_mean_var": [[m, v] for m, v, _ in out["levels"]],
             "multilevel_quantiles_N": {str(k): float(v) for k, v in zip(u, quant)}}
 
@@ -323,7 +336,7 @@ def plane_adaptive_leg(eps=50.0, n_warm=100):
                                            field_model="paper")
     out = mlmc.adaptive(run, eps, costs, dofs, n_warm=n_warm, alpha=None, alpha_default=0.5, refinement=4.0)
     return {"eps_N": eps, "levels_used": out["L"] + 1, "converged": out["converged"], "N": out["N"],
-            "estimate_N": out["estimate"], "sampling_std_N": out["sampling_variance"] ** 0.5,
+            "estimate_N": out["estimate"], "sampling_std_N": max(out["sampling_variance"], 0.0) ** 0.5,
             "bias_estimate_N": out["bias"], "alpha_fitted": out["history"][-1]["alpha"],
             "level_means_N": [m for m, _, _ in out["levels"]],
             "wall_s": out["wall_s"], "bond_updates_per_s": out["cost"] / out["wall_s"],
@@ -371,6 +384,8 @@ def main():
     ap.add_argument("--no-mlmc", action="store_true",
                     help="skip the three-level MLMC hierarchy (1024/128/16 samples + coupled partners), "
                          "which the default run times")
+    ap.add_argument("--mlmc-literal", action="store_true",
+                    help="also run the MLMC hierarchy on the literal (elastic) load")
     ap.add_argument("--mlmc-paper", action="store_true",
                     help="also run the MLMC hierarchy with the paper's material model (exponential covariance, "
                          "Weibull strength, fib relations)")
@@ -542,6 +557,8 @@ def main():
     if not args.no_mlmc:
         leg("mlmc_hierarchy", mlmc_leg, fracture=True)
         line["mlmc_samples_per_s"] = line["mlmc_hierarchy"]["mlmc_samples_per_s"]
+    if args.mlmc_literal:
+        leg("mlmc_hierarchy_literal", mlmc_leg, fracture=False)
     if args.mlmc_paper:
         leg("mlmc_hierarchy_paper_material", mlmc_leg, fracture=True, field_model="paper")
     if args.adaptive:
@@ -562,7 +579,7 @@ def main():
     if not args.no_cpu_baseline:
         leg("cpu_baseline", cpu_baseline)
 
-    print(json.dumps(line), flush=True)
+    print(json.dumps(finite_json(line)), flush=True)
 
 
 if __name__ == "__main__":

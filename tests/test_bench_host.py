@@ -41,3 +41,15 @@ def test_roofline_constants():
     assert bench.PEAK_HBM_GBPS == 8000.0
     assert bench.ALG_BYTES_PER_BOND_UPDATE_F32 == 7.8
     assert abs(bench.PEAK_TFLOPS_F32 - 157.2864) < 1e-9
+
+
+def test_bench_line_is_strict_json():
+    """Non-finite values (a rounding-negative variance's root, an empty
+    maximum) become null, so the line parses as strict JSON."""
+    import json
+    import math
+    import bench
+    line = {"a": float("nan"), "b": [1.0, float("inf"), {"c": -float("inf")}], "d": 2, "e": "x", "f": (3.0,)}
+    out = json.dumps(bench.finite_json(line), allow_nan=False)
+    assert json.loads(out) == {"a": None, "b": [1.0, None, {"c": None}], "d": 2, "e": "x", "f": [3.0]}
+    assert math.isfinite(bench.finite_json(1.5))
