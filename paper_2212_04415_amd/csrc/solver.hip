@@ -537,7 +537,14 @@ int pd_run_batch(const pd_batch_item *items, int32_t n_items, void *stream)
             if ((double)items[i].n_samples * items[i].mesh->M / ratio[i] >
                 (double)items[big].n_samples * items[big].mesh->M / ratio[big])
                 big = i;
-        for (int i = 0; i < n_items; ++i) solves[i].shape = solves[big].shape;
+        // one tick launch holds every item's work items: it too must stay
+        // below 2^32 work-items, else the batch keeps the branches
+        const int shape = solves[big].shape;
+        const LaunchShape &sh = kShapes[effective_shape(false, true, items[0].c != nullptr, shape)];
+        int64_t blocks = 0;
+        for (int i = 0; i < n_items; ++i) blocks += step_blocks(items[i].mesh, items[i].n_samples, sh);
+        if (blocks * sh.threads > (int64_t)UINT32_MAX) tick = false;
+        for (int i = 0; tick && i < n_items; ++i) solves[i].shape = shape;
     }
     hipGraphExec_t exec = nullptr;
     if (!rc && ticks > 0 && tick) {
