@@ -69,7 +69,8 @@ def build(verbose: bool = False) -> str:
     """Compiles every source to an object in parallel, then links.  The step
     kernels' register use is read from the compiler's resource remarks: an
     FP32 step kernel that spills registers fails the build (it would run
-    several times slower)."""
+    several times slower), and so does an FP32 kernel of the default brick
+    that needs more than 128 VGPRs (it would lose a wave per SIMD)."""
     from concurrent.futures import ThreadPoolExecutor
     import tempfile
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -94,6 +95,16 @@ def build(verbose: bool = False) -> str:
                 print(f"{k}: {v}", flush=True)
         if spilled:
             raise RuntimeError("FP32 step kernels spill registers: " + ", ".join(spilled))
+        # the default brick's FP32 kernels without a micromodulus tile hold 4
+        # waves per SIMD only up to 128 VGPRs (the 38.4 KB tile allows no
+        # more); a source change that pushes them past it costs a quarter of
+        # the throughput.  (With the c tile, LDS caps them at 3 anyway.)
+        import re
+        wide = [f"{k} ({v.get('VGPRs')} VGPRs)" for k, v in res.items()
+                if re.search(r"step_kernelIfLb[01]ELb0ELb1ENS_5BrickILi16ELi4ELi4ELi2E", k) and
+                v.get("VGPRs", 0) > 128]
+        if wide:
+            raise RuntimeError("FP32 16x4x4 step kernels need more than 128 VGPRs: " + ", ".join(wide))
         tmp = LIB + ".tmp"
         link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
         if verbose:

@@ -202,15 +202,14 @@ __device__ __forceinline__ T num_c(const typename Vec4<T>::t &ui, const typename
                                    T &ez)
 {
     static_assert(!PLANE || VY == 0, "in-plane offsets only");
+    // (the statement order of the 3D form is kept as it is: it decides the
+    // register allocation of the unrolled loop)
     ex = uj.x - ui.x;
+    if constexpr (PLANE) ey = T(0);
+    else ey = uj.y - ui.y;
     ez = uj.z - ui.z;
     T n = ex * term_c<VX, SIGN>(ex);
-    if constexpr (PLANE) {
-        ey = T(0);
-    } else {
-        ey = uj.y - ui.y;
-        n = fma_(ey, term_c<VY, SIGN>(ey), n);
-    }
+    if constexpr (!PLANE) n = fma_(ey, term_c<VY, SIGN>(ey), n);
     return fma_(ez, term_c<VZ, SIGN>(ez), n);
 }
 
