@@ -110,3 +110,29 @@ def test_tick_schedule_equals_the_branch_schedule(env, monkeypatch):
         assert torch.all(a[2] == 0)
         for x, y in zip(a, b):
             assert torch.equal(x, y)
+
+
+def test_runs_are_deterministic(env):
+    """Run to run, the batched FP32 path (damage developing: 32 level-1
+    samples on the cracking load for 3000 steps) repeats its peaks, peak
+    steps and final displacements bit for bit, and the FP64 single-sample
+    path its displacements and per-bond damage history: there are no atomics
+    or scheduling-dependent sums anywhere in the step."""
+    torch, B = env
+    lv = dataclasses.replace(W.level(1, fracture=True), n_steps=3000)
+    mesh = B.Mesh.for_level(lv)
+    g = torch.Generator("cuda").manual_seed(12)
+    s0 = W.S0_MEAN * (1.0 + 0.2 * torch.randn((32, mesh.n_nodes), dtype=torch.float64, device="cuda",
+                                              generator=g)).abs()
+    item = B.BatchItem(mesh, B.make_params(lv), 32, s0, want_u=True)
+    runs = [B.run_batch([item])[0] for _ in range(3)]
+    assert torch.all(runs[0][2] == 0)
+    for other in runs[1:]:
+        for x, y in zip(runs[0], other):
+            assert torch.equal(x, y)
+    l0 = dataclasses.replace(W.level(0, fracture=True), n_steps=2500)
+    m0 = B.Mesh.for_level(l0)
+    p = B.make_params(l0, precision="f64")
+    a, b = (B.run(m0, p, want_state=True) for _ in range(2))
+    assert np.count_nonzero(a["kappa"]) > 0
+    assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["kappa"], b["kappa"]) and a["Q"] == b["Q"]
