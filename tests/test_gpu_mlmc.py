@@ -253,3 +253,42 @@ def test_failed_samples_are_requeued_on_the_device():
     with pytest.raises(PM.SampleFailure) as ei:
         PM.run_batch_requeue([B.BatchItem(mesh, B.make_params(lv), 3, s0, c)])
     assert ei.value.failed == [(0, 2, pd.PD_ENONFINITE)]
+
+
+def test_three_level_hierarchy_at_full_size_sampled():
+    """The benchmarked MLMC configuration itself (three cracking-load levels,
+    1024 / 128 / 16 samples plus coupled partners, seed 2, one batched
+    call) checked on sampled solves: level-0 fine samples 0 and 1023 and
+    the coarse partners of level-1 samples 0 and 127, and level-1 fine
+    sample 0 and the coarse partner of level-2 sample 0, each re-solved by
+    the oracle on the same KL coefficients (peak within 0.5%); level-2 fine
+    sample 0 (16,000 steps, out of the oracle's reach) equals the same
+    sample solved alone, bit for bit."""
+    import torch
+    from paper_2212_04415_amd import beam as B
+    from paper_2212_04415_amd import mlmc as PM
+    levels = [W.level(l, fracture=True) for l in range(3)]
+    samples = [1024, 128, 16]
+    kw = dict(precision="f32", corr_len=W.FIELD_CORR_LEN, n_modes=W.FIELD_MODES, mean=W.S0_MEAN, cov=W.FIELD_COV,
+              kl_coefficients=W.kl_coefficients)
+    out = PM.coupled_batch(levels, samples, seed=2, **kw)
+    assert [q.size for q in out["Q"]] == [1152, 144, 16]
+    picks = {0: [(0, 0, 0), (1023, 0, 1023), (1024, 1, 0), (1151, 1, 127)], 1: [(0, 1, 0), (128, 2, 0)]}
+    jobs = []
+    for l, sel in picks.items():
+        lv = levels[l]
+        ob = OKL.Basis3D((lv.beam.length, lv.beam.thickness, lv.beam.depth), W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+        pos = G.node_positions(lv.shape, lv.dx)
+        for k, stream, row in sel:
+            xi = W.kl_coefficients(2, row + 1, stream=stream)[row:row + 1]
+            field = OKL.lognormal_field(ob, pos, xi, W.S0_MEAN, W.FIELD_COV)[0]
+            jobs.append((l, k, S.beam_problem(lv, s0=field)))
+    refs = [r["Q"] for r in S.run_many([j[2] for j in jobs], want_state=False)]
+    for (l, k, _), q in zip(jobs, refs):
+        assert out["Q"][l][k] == pytest.approx(q, rel=5e-3), (l, k, out["Q"][l][k], q)
+    lv2 = levels[2]
+    mesh = B.Mesh.for_level(lv2)
+    kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    s0 = kl.lognormal(torch.tensor(W.kl_coefficients(2, 1, stream=2)), W.S0_MEAN, W.FIELD_COV, dtype=torch.float32)
+    (Q, ns, st), = B.run_batch([B.BatchItem(mesh, B.make_params(lv2), 1, s0)])
+    assert int(st[0]) == 0 and Q[0].item() == out["Q"][2][0]
