@@ -50,10 +50,10 @@ FLOPS_PER_BOND_DIR_F32 = 38
 # 2.4 GHz = 157.3 TFLOP/s.
 PEAK_TFLOPS_F32 = 256 * 4 * 32 * 2 * 2.4e9 / 1e12
 # step-kernel instantiation per launch shape (FP32, compensated, no c field)
-SHAPE_NAMES = ["lds 16x4x4", "lds 8x8x4", "lds 8x4x4", "global 256"]
+SHAPE_NAMES = ["lds 16x4x4", "lds 8x8x4", "lds 12x4x4", "global 256"]
 SHAPE_KERNELS = ["step_kernel<float, true, false, true, Brick<16, 4, 4, 2>>",
                  "step_kernel<float, true, false, true, Brick<8, 8, 4>>",
-                 "step_kernel<float, true, false, true, Brick<8, 4, 4>>",
+                 "step_kernel<float, true, false, true, Brick<12, 4, 4>>",
                  "step_kernel<float, true, false, false, Brick<256, 1, 1>>"]
 
 

@@ -54,7 +54,9 @@ enum { PD_ACC_KAHAN = 0, PD_ACC_PLAIN = 1, PD_ACC_STATE_ONLY = 2, PD_ACC_FORCES_
 enum { PD_FIELD_S0 = 0, PD_FIELD_C = 1, PD_FIELD_GF = 2 };
 enum { PD_DTYPE_F32 = 0, PD_DTYPE_F64 = 1 };
 /* Launch shapes of the step kernel: nodes per block as an x-by-y-by-z brick
- * staged with its halo in LDS, or 256 consecutive nodes read through the
+ * staged with its halo in LDS (the 12x4x4 brick, 192 threads, wastes fewer
+ * lanes on meshes whose extents are not multiples of 16, such as the
+ * 35-node-long coarsest beam), or 256 consecutive nodes read through the
  * caches.  On a mesh one node thick (a plane body) the three brick shapes
  * are 64x4, 32x8 and 32x4 patches of the x-z plane.  All shapes give
  * bit-identical results. */
@@ -62,7 +64,7 @@ enum {
     PD_SHAPE_AUTO = -1,
     PD_SHAPE_LDS_16x4x4 = 0,
     PD_SHAPE_LDS_8x8x4 = 1,
-    PD_SHAPE_LDS_8x4x4 = 2,
+    PD_SHAPE_LDS_12x4x4 = 2,
     PD_SHAPE_GLOBAL_256 = 3,
     PD_N_SHAPES = 4
 };

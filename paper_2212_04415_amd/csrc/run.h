@@ -281,7 +281,7 @@ struct LaunchShape {
 constexpr LaunchShape kShapes[PD_N_SHAPES] = {
     {16, 4, 4, 256, true},   // PD_SHAPE_LDS_16x4x4
     {8, 8, 4, 256, true},    // PD_SHAPE_LDS_8x8x4
-    {8, 4, 4, 128, true},    // PD_SHAPE_LDS_8x4x4
+    {12, 4, 4, 192, true},   // PD_SHAPE_LDS_12x4x4
     {256, 1, 1, 256, false}, // PD_SHAPE_GLOBAL_256
 };
 // the same shape indices on a body one node thick: planar patches

@@ -20,7 +20,7 @@ static void launch_shape(int shape, bool plane, dim3 grid, hipStream_t st, const
             switch (shape) {
             case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<64, 4>><<<grid, 256, 0, st>>>(a); return;
             case PD_SHAPE_LDS_8x8x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<32, 8>><<<grid, 256, 0, st>>>(a); return;
-            case PD_SHAPE_LDS_8x4x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<32, 4>><<<grid, 128, 0, st>>>(a); return;
+            case PD_SHAPE_LDS_12x4x4: step_kernel<T, KAHAN, HAS_C, true, PlaneBrick<32, 4>><<<grid, 128, 0, st>>>(a); return;
             default: break;
             }
         } else if constexpr (sizeof(T) == 4) {
@@ -36,7 +36,7 @@ static void launch_shape(int shape, bool plane, dim3 grid, hipStream_t st, const
         switch (shape) {
         case PD_SHAPE_LDS_16x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<16, 4, 4, 2>><<<grid, 256, 0, st>>>(a); return;
         case PD_SHAPE_LDS_8x8x4: step_kernel<T, KAHAN, HAS_C, true, Brick<8, 8, 4>><<<grid, 256, 0, st>>>(a); return;
-        case PD_SHAPE_LDS_8x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<8, 4, 4>><<<grid, 128, 0, st>>>(a); return;
+        case PD_SHAPE_LDS_12x4x4: step_kernel<T, KAHAN, HAS_C, true, Brick<12, 4, 4>><<<grid, 192, 0, st>>>(a); return;
         default: break;
         }
     } else if constexpr (sizeof(T) == 4) {
@@ -56,7 +56,7 @@ static void launch_tick_shape(int shape, dim3 grid, hipStream_t st, const TickPa
     switch (shape) {
     case PD_SHAPE_LDS_16x4x4: step_kernel_tick<float, true, HAS_C, true, Brick<16, 4, 4, 2>><<<grid, 256, 0, st>>>(m); return;
     case PD_SHAPE_LDS_8x8x4: step_kernel_tick<float, true, HAS_C, true, Brick<8, 8, 4>><<<grid, 256, 0, st>>>(m); return;
-    case PD_SHAPE_LDS_8x4x4: step_kernel_tick<float, true, HAS_C, true, Brick<8, 4, 4>><<<grid, 128, 0, st>>>(m); return;
+    case PD_SHAPE_LDS_12x4x4: step_kernel_tick<float, true, HAS_C, true, Brick<12, 4, 4>><<<grid, 192, 0, st>>>(m); return;
     default: step_kernel_tick<float, true, HAS_C, false, Brick<256, 1, 1>><<<grid, 256, 0, st>>>(m); return;
     }
 }

@@ -18,7 +18,7 @@ PD_FP32, PD_FP64 = 0, 1
 PD_ACC_KAHAN, PD_ACC_PLAIN, PD_ACC_STATE_ONLY, PD_ACC_FORCES_ONLY = 0, 1, 2, 3
 PD_FIELD_S0, PD_FIELD_C, PD_FIELD_GF = 0, 1, 2
 PD_DTYPE_F32, PD_DTYPE_F64 = 0, 1
-PD_SHAPE_AUTO, PD_SHAPE_LDS_16x4x4, PD_SHAPE_LDS_8x8x4, PD_SHAPE_LDS_8x4x4, PD_SHAPE_GLOBAL_256 = -1, 0, 1, 2, 3
+PD_SHAPE_AUTO, PD_SHAPE_LDS_16x4x4, PD_SHAPE_LDS_8x8x4, PD_SHAPE_LDS_12x4x4, PD_SHAPE_GLOBAL_256 = -1, 0, 1, 2, 3
 PD_N_SHAPES = 4
 PD_MAX_CDF_LEVELS = 8
 PD_COV_SQEXP, PD_COV_EXP = 0, 1
