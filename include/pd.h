@@ -44,7 +44,7 @@ enum {
     PD_ENOMEM = -2,      /* host or device allocation failed */
     PD_EDEVICE = -3,     /* HIP runtime error, or the HIP device is missing */
     PD_EUNSTABLE = -4,   /* dt above the explicit stability limit */
-    PD_ENONFINITE = -5,  /* a run produced a non-finite reaction */
+    PD_ENONFINITE = -5,  /* a run went non-finite (reaction or node state) */
     PD_ESTATE = -6       /* call out of order (e.g. bonds not built) */
 };
 

@@ -213,3 +213,17 @@ def test_params_come_from_the_level_description():
                     assert all(a.name != "workloads" for a in node.names), name
                 if isinstance(node, ast.ImportFrom):
                     assert node.module != "workloads", name
+
+
+def test_binding_constants_match_the_header():
+    """Every enum constant of include/pd.h has the same value in the Python
+    binding (a renamed or renumbered constant fails here, not on a GPU)."""
+    text = open(os.path.join(ROOT, "include", "pd.h")).read()
+    consts = {}
+    for body in re.findall(r"enum\s*\{([^}]*)\}", text):
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        for name, value in re.findall(r"(PD_[A-Z0-9_x]+)\s*=\s*(-?\d+)", body):
+            consts[name] = int(value)
+    assert len(consts) >= 29
+    for name, value in consts.items():
+        assert getattr(pd, name) == value, name
