@@ -188,7 +188,10 @@ PD_API int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const
  * supports u_z = 0 and the load pad u_z = -(n+1) du; L = force(u) with the
  * irreversible damage history; v = (v + (dt/2rho) L) / (1 + damping dt/2rho);
  * R^{n+1} = -sum_{supports} L_z V; Q = max_n R^n (section 4 QoI: peak load).
- * *out receives a run handle; read it with pd_qoi / pd_run_state. */
+ * *out receives a run handle; read it with pd_qoi / pd_run_state.  Returns
+ * PD_EUNSTABLE, before enqueuing anything, when dt exceeds the explicit
+ * stability limit of the largest micromodulus (the mesh's c field if set,
+ * else the homogeneous value). */
 PD_API int pd_run(pd_mesh m, const pd_params *p, void *stream, pd_run_h *out);
 
 /* Peak reaction Q = max_n R^n (N; the peak load of the beam, section 4),
