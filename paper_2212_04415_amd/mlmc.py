@@ -288,39 +288,41 @@ def adaptive(run: Callable, eps: float, costs: Sequence[float], dofs: Sequence[f
         dev = torch.tensor(np.stack(sums), dtype=torch.float64, device="cuda")
         return B.mlmc_estimate(list(dev), stream=stream)
 
-    L = 0
-    converged = False
-    while True:
-        N.append(0)
-        sums.append(np.zeros(3))
-        take({L: n_warm})
-        est = moments()
-        V = [max(lv[1], 0.0) for lv in est["levels"]]   # rounding can push Eq. sample_variance below 0
-        _, n_hat = allocation(V, costs[:L + 1], eps_s)
-        extra = {l: int(n_hat[l]) - N[l] for l in range(L + 1) if int(n_hat[l]) > N[l]}
-        if extra:
-            take(extra)
+    try:
+        L = 0
+        converged = False
+        while True:
+            N.append(0)
+            sums.append(np.zeros(3))
+            take({L: n_warm})
             est = moments()
-        means = [lv[0] for lv in est["levels"]]
-        if alpha is not None:
-            a = alpha
-        elif L >= 2:
-            a = -fit_rate(dofs[1:L + 1], means[1:L + 1])[0]
-        else:
-            a = alpha_default
-        # Eq. bias_error needs a positive rate; corrections that do not decay
-        # (fitted alpha <= 0) leave the bias unbounded
-        b = bias(means[L], a, refinement, r) if r * refinement ** a > 1.0 else float("inf")
-        history.append(dict(L=L, V=list(V), n_hat=[int(v) for v in n_hat], N=list(N), alpha=a, bias=b))
-        if b < eps_b:
-            converged = True
-            break
-        if L == last:
-            break
-        L += 1
-    est = moments()
-    if sink is not None:
-        sink.close()
+            V = [max(lv[1], 0.0) for lv in est["levels"]]   # rounding can push Eq. sample_variance below 0
+            _, n_hat = allocation(V, costs[:L + 1], eps_s)
+            extra = {l: int(n_hat[l]) - N[l] for l in range(L + 1) if int(n_hat[l]) > N[l]}
+            if extra:
+                take(extra)
+                est = moments()
+            means = [lv[0] for lv in est["levels"]]
+            if alpha is not None:
+                a = alpha
+            elif L >= 2:
+                a = -fit_rate(dofs[1:L + 1], means[1:L + 1])[0]
+            else:
+                a = alpha_default
+            # Eq. bias_error needs a positive rate; corrections that do not decay
+            # (fitted alpha <= 0) leave the bias unbounded
+            b = bias(means[L], a, refinement, r) if r * refinement ** a > 1.0 else float("inf")
+            history.append(dict(L=L, V=list(V), n_hat=[int(v) for v in n_hat], N=list(N), alpha=a, bias=b))
+            if b < eps_b:
+                converged = True
+                break
+            if L == last:
+                break
+            L += 1
+        est = moments()
+    finally:
+        if sink is not None:
+            sink.close()
     return dict(L=L, N=N, sums=[tuple(x) for x in sums], estimate=est["estimate"],
                 sampling_variance=est["sampling_variance"], levels=est["levels"], bias=history[-1]["bias"],
                 converged=converged, history=history, eps_s=eps_s, eps_b=eps_b, wall_s=wall,
