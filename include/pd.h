@@ -218,8 +218,9 @@ PD_API int pd_free_run(pd_run_h r);
  * c (micromodulus, device or NULL), gf (fracture energy in N/m, device or
  * NULL = homogeneous p->GF); outputs qoi (device FP64 [n_samples]), nstar (device
  * int64 [n_samples], nullable), status (device int32 [n_samples], nullable;
- * PD_OK, PD_ENONFINITE, or PD_EUNSTABLE for a sample whose micromodulus
- * field exceeds what dt allows), u_out (device FP64 [n_samples][n_nodes][3],
+ * PD_OK, PD_ENONFINITE, PD_EUNSTABLE for a sample whose micromodulus
+ * field exceeds what dt allows, or PD_EINVAL for one whose micromodulus
+ * field has a value that is not positive), u_out (device FP64 [n_samples][n_nodes][3],
  * nullable: each sample's displacement after its last step, in metres).
  * These are the independent level-l solves of one MLMC sweep (section 3,
  * Eq. MLMC_estimator and Algorithm 1): each sample runs the explicit solve

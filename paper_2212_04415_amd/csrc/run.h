@@ -23,10 +23,13 @@ namespace pdmi {
 template <typename T>
 __global__ void init_state_kernel(typename Vec4<T>::t *u0, typename Vec4<T>::t *u1, int64_t P, int64_t S,
                                   int nx, int ny, int nz, int PX, int64_t PXY, const NodeInfo *info,
-                                  double load0)
+                                  double load0, const T *cpad)
 {
-    // every padded cell of every sample (grid-stride); real nodes get flag 1
-    // and the first prescribed load displacement, ghosts are all zero
+    // every padded cell of every sample (grid-stride); real nodes get the
+    // flag word (1, or with a micromodulus field on a 3D body their c / c_ref,
+    // which the step kernel reads from there; its sign later marks a node
+    // that has had an exceptional bond) and the first prescribed load
+    // displacement, ghosts are all zero
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < P * S;
          g += (int64_t)gridDim.x * blockDim.x) {
     int64_t q = g % P;
@@ -38,7 +41,7 @@ __global__ void init_state_kernel(typename Vec4<T>::t *u0, typename Vec4<T>::t *
     V4 v{};
     if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) {
         int64_t node = i + (int64_t)nx * (j + (int64_t)ny * k);
-        v.w = T(1);
+        v.w = cpad ? cpad[g] : T(1);
         if (info[node].bc == -2) v.z = (T)load0;
     }
     u0[g] = v;
@@ -110,24 +113,38 @@ static __global__ void init_qoi_kernel(double *Q, int64_t *nstar, int32_t *statu
     }
 }
 
-// Per-sample largest value of a positive field [S][M] of type In, compared
-// with `limit`: a sample whose field exceeds it gets `code` in status (the
-// explicit step is unstable where the micromodulus exceeds the value its
-// time step allows).  One block per sample.
+// Per-sample check of a micromodulus field [S][M] of type In: a sample
+// with a value that is not positive gets PD_EINVAL in status (the step
+// kernel keeps c / c_ref in the flag word, where 0 marks a ghost cell and
+// the sign a node with an exceptional bond), else, when its largest value
+// exceeds `limit`, `code` (the explicit step is unstable where the
+// micromodulus exceeds the value its time step allows).  NaN passes, and the
+// run then reports it as non-finite.  One block per sample.
 template <typename In>
 __global__ void field_limit_kernel(const In *f, int64_t M, double limit, int32_t code, int32_t *status)
 {
     __shared__ double part[256];
+    __shared__ int nonpos;
+    if (threadIdx.x == 0) nonpos = 0;
+    __syncthreads();
     const In *x = f + (int64_t)blockIdx.x * M;
     double mx = 0.0;
-    for (int64_t i = threadIdx.x; i < M; i += blockDim.x) mx = fmax(mx, (double)x[i]);
+    bool bad = false;
+    for (int64_t i = threadIdx.x; i < M; i += blockDim.x) {
+        mx = fmax(mx, (double)x[i]);
+        bad = bad || x[i] <= In(0);
+    }
     part[threadIdx.x] = mx;
+    if (bad) nonpos = 1;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0 && part[0] > limit) status[blockIdx.x] = code;
+    if (threadIdx.x == 0) {
+        if (nonpos) status[blockIdx.x] = PD_EINVAL;
+        else if (part[0] > limit) status[blockIdx.x] = code;
+    }
 }
 
 // FP64 copy of a device field with its largest value and a count of values
@@ -462,9 +479,6 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
     const pd_mesh_s *m = s.m;
     int64_t S = s.b.S;
     unsigned nb = stride_blocks(m->P * S);
-    init_state_kernel<T><<<nb, 256, 0, st>>>((typename Vec4<T>::t *)s.b.u[0], (typename Vec4<T>::t *)s.b.u[1], m->P,
-                                             S, m->nx, m->ny, m->nz, m->PX, (int64_t)m->PX * m->PY, m->d_info,
-                                             -s.p.du / m->d.dx);
     int64_t nv = vel_components(m) * m->M * S;
     fill_kernel<T><<<stride_blocks(nv), 256, 0, st>>>((T *)s.b.vh, nv, T(0));
     if (s.b.comp_state) {
@@ -479,6 +493,11 @@ static int setup_solve(Solve &s, const In *s0, int64_t s0_stride, const In *c, i
                                              s.b.has_g ? gf : nullptr, s.p.s0,
                                              1.0 / s.mat.c_ref, 1.0 / s.p.GF, m->P, m->M, S, m->nx, m->ny, m->nz,
                                              m->PX, (int64_t)m->PX * m->PY, s0_stride, c_stride, gf_stride);
+    // after the fields: the flag words carry the padded c / c_ref
+    init_state_kernel<T><<<nb, 256, 0, st>>>((typename Vec4<T>::t *)s.b.u[0], (typename Vec4<T>::t *)s.b.u[1], m->P,
+                                             S, m->nx, m->ny, m->nz, m->PX, (int64_t)m->PX * m->PY, m->d_info,
+                                             -s.p.du / m->d.dx,
+                                             s.b.has_c && !plane_mesh(m) ? (const T *)s.b.cpad : nullptr);
     threshold_kernel<T><<<stride_blocks(m->M * S), 256, 0, st>>>((T *)s.b.thr, (const T *)s.b.s0pad, m->P, m->M, S,
                                                               m->nx, m->ny, m->PX, (int64_t)m->PX * m->PY);
     init_qoi_kernel<<<stride_blocks(S), 256, 0, st>>>(s.b.Q, s.b.nstar, s.b.status, s.b.step, S);

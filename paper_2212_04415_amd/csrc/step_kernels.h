@@ -423,12 +423,18 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
 {
     using PO = Pairs<PLANE>;
     constexpr int NP = PO::order.n;
+    // a 3D body keeps a node's c / c_ref in its flag word (a plane body, with
+    // its small c tile, keeps the tile: its registers are the tighter limit)
+    constexpr bool CW = HAS_C && !PLANE;
     auto load = [&](auto ic) {
         constexpr Off v = kHalf.v[PO::order.k[decltype(ic)::value]];
         FastLoad<T> r;
         r.a = src.template get<v.x, v.y, v.z>();
         r.b = src.template get<-v.x, -v.y, -v.z>();
-        if constexpr (HAS_C) {
+        if constexpr (CW) {
+            r.ca = fabs(r.a.w);
+            r.cb = fabs(r.b.w);
+        } else if constexpr (HAS_C) {
             r.ca = src.template getc<v.x, v.y, v.z>();
             r.cb = src.template getc<-v.x, -v.y, -v.z>();
         } else {
@@ -457,7 +463,9 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
             constexpr double h = 0.5 / V2, L = kSqrtInt[V2];
             constexpr T C1 = T(h / L), C2 = T(-1.5 * h * h / L), C3 = T(2.5 * h * h * h / L);
             constexpr T S2 = T(2 * V2);
-            const T nwa = na * fabs(r.a.w), nwb = nb * fabs(r.b.w);
+            // ghost neighbours (flag word 0) contribute nothing
+            const T nwa = CW ? (r.a.w != T(0) ? na : T(0)) : na * fabs(r.a.w);
+            const T nwb = CW ? (r.b.w != T(0) ? nb : T(0)) : nb * fabs(r.b.w);
             wa = nwa * fma_(na, fma_(na, C3, C2), C1);
             wb = nwb * fma_(nb, fma_(nb, C3, C2), C1);
             if constexpr (MASKED) {
@@ -478,8 +486,10 @@ __device__ __forceinline__ void fast_loop(const StepParams<T> &a, const Src &src
             }
         } else {
             T rya, ryb;
-            const T sa = stretch_from_num(na, T(V2), T(kSqrtInt[V2]), rya) * fabs(r.a.w);
-            const T sb = stretch_from_num(nb, T(V2), T(kSqrtInt[V2]), ryb) * fabs(r.b.w);
+            const T sa0 = stretch_from_num(na, T(V2), T(kSqrtInt[V2]), rya);
+            const T sb0 = stretch_from_num(nb, T(V2), T(kSqrtInt[V2]), ryb);
+            const T sa = CW ? (r.a.w != T(0) ? sa0 : T(0)) : sa0 * fabs(r.a.w);
+            const T sb = CW ? (r.b.w != T(0) ? sb0 : T(0)) : sb0 * fabs(r.b.w);
             if constexpr (MASKED) {
                 exa = sa > thr;
                 exb = sb > thr;
@@ -680,7 +690,7 @@ struct ExcFetch {
     int x, y, z, len2;
 };
 
-template <typename T, bool HAS_C, typename Src>
+template <typename T, bool HAS_C, bool CW, typename Src>
 __device__ __forceinline__ ExcFetch<T> exc_fetch(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
                                                  const T *__restrict__ S0, const T *__restrict__ Hs,
                                                  const T *__restrict__ Gp, int gstep, uint32_t lb1, uint32_t lbh,
@@ -697,7 +707,8 @@ __device__ __forceinline__ ExcFetch<T> exc_fetch(const StepParams<T> &a, const S
     f.s0j = ld(S0, off, lb1);
     f.gj = ld(Gp, off * gstep, lb1 * (uint32_t)gstep);
     f.cj = T(1);
-    if constexpr (HAS_C) f.cj = src.getc(f.x, f.y, f.z);
+    if constexpr (CW) f.cj = fabs(f.uj.w);
+    else if constexpr (HAS_C) f.cj = src.getc(f.x, f.y, f.z);
     const T *H = (const T *)((const char *)(Hs + (int64_t)k * a.M) + lbh);
     f.kap = was ? *H : T(0);
     return f;
@@ -749,7 +760,7 @@ __device__ __forceinline__ bool exc_finish(const StepParams<T> &a, const SlotLds
 // node's force is bit-identical to a walk over its own bonds.  Called by
 // every lane of the wave (lanes without a node pass todo = 0); list is this
 // wave's 128-entry slice of block-shared memory.
-template <typename T, bool KAHAN, bool HAS_C, typename Src>
+template <typename T, bool KAHAN, bool HAS_C, bool CW, typename Src>
 __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src, const SlotLds<T> &tab,
                                          const T *__restrict__ S0, T *__restrict__ Hs, const T *__restrict__ Gp,
                                          int gstep, uint32_t p, uint32_t node, const typename Vec4<T>::t &ui,
@@ -807,10 +818,10 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
         const uint32_t lh0 = n0 * (uint32_t)sizeof(T), lh1 = n1 * (uint32_t)sizeof(T);
         ExcFetch<T> f0, f1;
         if (has0)
-            f0 = exc_fetch<T, HAS_C>(a, src.rebased(k0), tab, S0, Hs, Gp, gstep, p0 * (uint32_t)sizeof(T), lh0,
+            f0 = exc_fetch<T, HAS_C, CW>(a, src.rebased(k0), tab, S0, Hs, Gp, gstep, p0 * (uint32_t)sizeof(T), lh0,
                                      (int)(ent0 & 127u), (ent0 & 128u) != 0u);
         if (has1)
-            f1 = exc_fetch<T, HAS_C>(a, src.rebased(k1), tab, S0, Hs, Gp, gstep, p1 * (uint32_t)sizeof(T), lh1,
+            f1 = exc_fetch<T, HAS_C, CW>(a, src.rebased(k1), tab, S0, Hs, Gp, gstep, p1 * (uint32_t)sizeof(T), lh1,
                                      (int)(ent1 & 127u), (ent1 & 128u) != 0u);
         T fx0 = T(0), fy0 = T(0), fz0 = T(0), fx1 = T(0), fy1 = T(0), fz1 = T(0);
         bool now0 = false, live0 = false, now1 = false, live1 = false;
@@ -903,10 +914,11 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
 {
     using V4 = typename Vec4<T>::t;
     const T *__restrict__ S0 = a.s0pad + (int64_t)sample * a.P;
+    constexpr bool CW = HAS_C && !PLANE;   // c / c_ref in the flag word (3D)
     const T *__restrict__ Cp = HAS_C ? a.cpad + (int64_t)sample * a.P : nullptr;
     const int64_t sm = (int64_t)sample * a.M + node;
     const NodeInfo inf = valid ? a.info[node] : NodeInfo{-1, -1};
-    const T ci = (HAS_C && valid) ? Cp[p] : T(1);
+    const T ci = !(HAS_C && valid) ? T(1) : CW ? fabs(ui.w) : Cp[p];
     // without a fracture-energy field every bond reads the one unit value
     const int gstep = a.gstep;
     const T *__restrict__ Gp = a.gpad + (int64_t)sample * a.P * gstep;
@@ -960,7 +972,7 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         T *Hs = a.hist + (int64_t)sample * kStencil * a.M;
         const T s0i = valid ? S0[p] : T(1);
         const T gi = valid ? ld(Gp, p * gstep, 0u) : T(1);
-        exc_pool<T, KF, HAS_C>(a, src, tab, S0, Hs, Gp, gstep, (uint32_t)p, (uint32_t)node, ui, s0i, ci, gi, todo,
+        exc_pool<T, KF, HAS_C, CW>(a, src, tab, S0, Hs, Gp, gstep, (uint32_t)p, (uint32_t)node, ui, s0i, ci, gi, todo,
                                   dm, acc, list);
     }
     if (!valid) return;
@@ -1016,7 +1028,8 @@ __device__ __forceinline__ void node_step(const StepParams<T> &a, const Src &src
         a.rf[(int64_t)(n & 1) * a.rf_stride + (int64_t)sample * a.nsup + inf.bc] =
             (double)acc.z - (KF ? (double)acc.cz : 0.0);
     }
-    un.w = dirty ? T(-1) : T(1);
+    const T wn = CW ? ci : T(1);
+    un.w = dirty ? -wn : wn;
     // every 64 steps (and at the last): a node whose state left the finite
     // numbers marks its sample (the reaction alone misses nodes away from
     // the supports); a status set earlier (an unstable field) is kept
@@ -1070,7 +1083,7 @@ __device__ __forceinline__ void step_tile(const StepParams<T> &a, int64_t item)
 {
     using V4 = typename Vec4<T>::t;
     __shared__ V4 tile[LDS ? BR::TILE : 1];
-    __shared__ T ctile[(LDS && HAS_C) ? BR::TILE : 1];
+    __shared__ T ctile[(LDS && HAS_C && BR::PLANE) ? BR::TILE : 1];
     __shared__ SlotLds<T> tab;
     // the previous reaction's partial sums, then each wave's exception list
     __shared__ double scratch[128];
@@ -1118,7 +1131,8 @@ __device__ __forceinline__ void step_tile(const StepParams<T> &a, int64_t item)
             V4 v{};
             if (in) v = U[gi];
             tile[lx + BR::LX * ly + BR::LXY * lz] = v;
-            if constexpr (HAS_C) ctile[lx + BR::LX * ly + BR::LXY * lz] = in ? a.cpad[(int64_t)sample * a.P + gi] : T(0);
+            if constexpr (HAS_C && BR::PLANE)
+                ctile[lx + BR::LX * ly + BR::LXY * lz] = in ? a.cpad[(int64_t)sample * a.P + gi] : T(0);
         }
         __syncthreads();
         const int tx = threadIdx.x % BR::BX, ty = (threadIdx.x / BR::BX) % BR::BY, tz = threadIdx.x / (BR::BX * BR::BY);

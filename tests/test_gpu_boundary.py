@@ -182,3 +182,20 @@ def test_batch_returns_before_the_solve_ends(env):
 def C_stream(torch):
     import ctypes
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def test_batch_flags_a_non_positive_micromodulus(env):
+    """A batch sample whose micromodulus field has a zero or a negative value
+    gets PD_EINVAL (the kernels keep c / c_ref in the flag word, where 0
+    marks a ghost cell); its neighbours in the batch are unaffected."""
+    torch, B, pd = env
+    lv = dataclasses.replace(W.level(0, fracture=True), n_steps=32)
+    mesh = B.Mesh.for_level(lv)
+    p = B.make_params(lv)
+    c = torch.full((3, mesh.n_nodes), c_ref(lv), dtype=torch.float64, device="cuda")
+    (Qa, na, sa), = B.run_batch([B.BatchItem(mesh, p, 1, None, c[:1].contiguous())])
+    c[1, 100] = 0.0
+    c[2, 7] = -c_ref(lv)
+    (Q, ns, st), = B.run_batch([B.BatchItem(mesh, p, 3, None, c)])
+    assert st.tolist() == [pd.PD_OK, pd.PD_EINVAL, pd.PD_EINVAL]
+    assert Q[0] == Qa[0] and ns[0] == na[0]
