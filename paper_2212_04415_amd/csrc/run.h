@@ -49,6 +49,16 @@ __global__ void init_state_kernel(typename Vec4<T>::t *u0, typename Vec4<T>::t *
     }
 }
 
+// Flag words of displacement cells written from the host (1 for a real
+// node, 0 for a ghost): a real node's word becomes its c / c_ref, as
+// init_state_kernel sets it on a 3D body with a micromodulus field.
+template <typename T>
+__global__ void flag_from_c_kernel(typename Vec4<T>::t *u, const T *cpad, int64_t n)
+{
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+        if (u[g].w != T(0)) u[g].w = cpad[g];
+}
+
 template <typename T, typename In>
 __global__ void fields_kernel(T *s0pad, T *cpad, T *gpad, const In *s0, const In *c, const In *gf, double s0_const,
                               double inv_cref, double inv_gref, int64_t P, int64_t M, int64_t S, int nx, int ny,

@@ -237,7 +237,7 @@ int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double
         else rc = setup_solve<float>(s, m->d_s0, m->M, m->d_c, m->M, st, m->d_gf, m->M);
         if (rc) break;
         s.shape = known_shape(s);
-        // displacements into the padded grid (units of dx), flag 1
+        // displacements into the padded grid (units of dx), flag 1 (0 in ghosts)
         host.assign(ts * 4 * m->P * n_samples, 0);
         for (int64_t smp = 0; smp < n_samples; ++smp)
             for (int k = 0; k < m->nz; ++k)
@@ -254,6 +254,12 @@ int pd_force_eval(pd_mesh m, const pd_params *p, int64_t n_samples, const double
                     }
         hipError_t e = hipMemcpyAsync(s.b.u[0], host.data(), host.size(), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) { rc = hip_fail(e, "upload u"); break; }
+        if (s.b.has_c && !plane_mesh(m)) {
+            // a 3D body keeps each node's c / c_ref in its flag word
+            const int64_t n = m->P * n_samples;
+            if (f64) flag_from_c_kernel<double><<<stride_blocks(n), 256, 0, st>>>((double4 *)s.b.u[0], (const double *)s.b.cpad, n);
+            else flag_from_c_kernel<float><<<stride_blocks(n), 256, 0, st>>>((float4 *)s.b.u[0], (const float *)s.b.cpad, n);
+        }
         e = hipMalloc(&dL, 8 * 3 * m->M * n_samples);
         if (e != hipSuccess) { rc = hip_fail(e, "hipMalloc(L)"); break; }
         if (f64) launch_step<double>(s, 0, st, dL);
