@@ -343,6 +343,64 @@ def plane_adaptive_leg(eps=50.0, n_warm=100):
             "mlmc_samples_per_s": sum(out["N"]) / out["wall_s"]}
 
 
+def adjoint_leg(oracle_steps=400):
+    """The gradient workload: level 1, one lognormal-field sample (seed 3),
+    the cracking load with the exponential-linear law, 8000 steps,
+    checkpoints every 200.  Wall time of pd_qoi_grad (peak, dQ/ds0 and dQ/dc)
+    in FP64 and FP32 beside the forward solve alone (pd_run), and the
+    oracle's discrete adjoint (C, all host threads) over the first
+    oracle_steps steps of the same sample, with its per-step time scaled to
+    the full run (labelled as such)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import solver as S
+    from paper_2212_04415_amd import beam as B
+    from paper_2212_04415_amd import pd
+    lv = W.level(1, fracture=True, law=W.LAW_EXPLIN)
+    mesh = B.Mesh.for_level(lv)
+    kl = B.KL(mesh, W.FIELD_CORR_LEN, W.FIELD_MODES, 256)
+    s0 = kl.lognormal(torch.tensor(W.kl_coefficients(3, 1)), W.S0_MEAN, W.FIELD_COV, dtype=torch.float64)[0]
+    out = {"workload": "level-1 beam, 1 sample, 8000 steps, checkpoints every 200", "steps": lv.n_steps}
+    for prec in ("f64", "f32"):
+        p = B.make_params(lv, precision=prec, checkpoint_every=200)
+        mesh.set_field(pd.PD_FIELD_S0, s0.cpu().numpy())
+        B.run(mesh, B.make_params(lv, precision=prec, n_steps=64))      # tunes the launch shape
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fwd = B.run(mesh, p)
+        forward_s = time.perf_counter() - t
+        mesh.set_field(pd.PD_FIELD_S0, None)
+        t = time.perf_counter()
+        g = B.qoi_grad(mesh, p, s0=s0, as_tensors=True)
+        torch.cuda.synchronize()
+        grad_s = time.perf_counter() - t
+        out[prec] = {"grad_s": grad_s, "forward_s": forward_s, "grad_over_forward": grad_s / forward_s,
+                     "peak_N": g["Q"], "nstar": g["nstar"], "forward_peak_N": fwd["Q"],
+                     "dQ_ds0_norm": float(torch.linalg.vector_norm(g["dQ_ds0"])),
+                     "dQ_dc_norm": float(torch.linalg.vector_norm(g["dQ_dc"]))}
+    threads = host_threads()
+    S.set_threads(threads)
+    prob = S.beam_problem(lv, s0=s0.cpu().numpy(), n_steps=oracle_steps)
+    t = time.perf_counter()
+    prob.run(want_state=False)
+    fwd_s = time.perf_counter() - t
+    t = time.perf_counter()
+    a = prob.adjoint()
+    adj_s = time.perf_counter() - t
+    # the oracle's adjoint is one forward sweep over every step (trajectory
+    # kept) and one backward sweep from the peak step down to step 0
+    back_per_step = max(adj_s - fwd_s, 0.0) / max(a["nstar"], 1)
+    nstar = out["f64"]["nstar"]
+    out["oracle"] = {"steps": oracle_steps, "threads": threads, "cpu_model": cpu_model(),
+                     "forward_s": fwd_s, "adjoint_s": adj_s, "adjoint_nstar": a["nstar"],
+                     "estimated_full_s": fwd_s / oracle_steps * lv.n_steps + back_per_step * nstar,
+                     "note": f"estimate: forward and backward per-step times of the first {oracle_steps} (elastic) "
+                             f"steps, times {lv.n_steps} forward and {nstar} backward steps"}
+    out["f64"]["speedup_vs_oracle_estimate"] = out["oracle"]["estimated_full_s"] / out["f64"]["grad_s"]
+    return out
+
+
 def cost_curve_leg(eps_list=(100.0, 50.0, 25.0, 10.0 * 2 ** 0.5), n_warm=100):
     """Cost of the adaptive estimator against the RMSE target (the last one
     splits into the paper's 10 N sampling tolerance) on the plane-stress
@@ -404,6 +462,9 @@ def main():
                          "50 N sampling tolerance (1624/479/230/63/22 samples)")
     ap.add_argument("--plane-adaptive", action="store_true",
                     help="also run the adaptive MLMC algorithm on the plane-stress Specimen 3 (RMSE target 50 N)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the gradient (pd_qoi_grad, FP64 and FP32) on the level-1 sample beside the "
+                         "forward solve and the oracle's adjoint")
     ap.add_argument("--cost-curve", action="store_true",
                     help="also run the adaptive MLMC on the plane-stress Specimen 3 at eps = 100 / 50 / 25 / 14.1 N "
                          "(the last: a 10 N sampling tolerance, as in the paper's allocation table)")
@@ -575,6 +636,8 @@ def main():
         leg("plane_stress_mlmc_adaptive", plane_adaptive_leg)
     if args.cost_curve:
         leg("plane_stress_cost_curve", cost_curve_leg)
+    if args.adjoint:
+        leg("adjoint", adjoint_leg)
 
     if not args.no_cpu_baseline:
         leg("cpu_baseline", cpu_baseline)
