@@ -629,49 +629,42 @@ __device__ __forceinline__ double shfl_t(double v, uint32_t src)
     return __builtin_bit_cast(double, lo | (hi << 32));
 }
 
-// Bit k of a 128-bit mask held in four registers (selects, not an indexed
-// array, so the mask stays in registers).
+// Bit k of a 128-bit mask held in four registers.  The helpers below are
+// written as selects on values (range tests, no chains of equality tests,
+// which the compiler turns into switches and then into branches): they run
+// once per round of the exception pass on diverged lanes, where every branch
+// costs exec-mask updates on the scalar unit.
 __device__ __forceinline__ bool mask_bit(const uint32_t (&m)[4], int k)
 {
-    const int w = k >> 5;
-    const uint32_t v = w == 0 ? m[0] : w == 1 ? m[1] : w == 2 ? m[2] : m[3];
-    return (v >> (k & 31)) & 1u;
+    const uint32_t lo = k < 32 ? m[0] : m[1], hi = k < 96 ? m[2] : m[3];
+    return ((k < 64 ? lo : hi) >> (k & 31)) & 1u;
 }
-__device__ __forceinline__ void set_mask_bit(uint32_t (&m)[4], int k)
+// Sets bit k when on is true.
+__device__ __forceinline__ void set_mask_bit(uint32_t (&m)[4], int k, bool on = true)
 {
-    const int w = k >> 5;
-    const uint32_t b = 1u << (k & 31);
-    m[0] |= w == 0 ? b : 0u;
-    m[1] |= w == 1 ? b : 0u;
-    m[2] |= w == 2 ? b : 0u;
-    m[3] |= w == 3 ? b : 0u;
+    const uint32_t b = on ? 1u << (k & 31) : 0u;
+    m[0] |= k < 32 ? b : 0u;
+    m[1] |= (k >= 32 && k < 64) ? b : 0u;
+    m[2] |= (k >= 64 && k < 96) ? b : 0u;
+    m[3] |= k >= 96 ? b : 0u;
 }
 
-// Takes the lowest set bit of the 128-bit mask m (word order 0..3) and
-// returns its slot, or -1 when m is empty.
-__device__ __forceinline__ int pop_slot(uint32_t (&m)[4])
+// The lowest set bit of the 128-bit mask m (word order 0..3): its slot, or -1
+// when m is empty.  Stored back into m with that bit cleared only when take
+// is true, so lanes that sit a round out keep their mask.
+__device__ __forceinline__ int pop_slot(uint32_t (&m)[4], bool take = true)
 {
-    if (m[0]) {
-        const int b = __builtin_ctz(m[0]);
-        m[0] &= m[0] - 1u;
-        return b;
-    }
-    if (m[1]) {
-        const int b = __builtin_ctz(m[1]);
-        m[1] &= m[1] - 1u;
-        return 32 + b;
-    }
-    if (m[2]) {
-        const int b = __builtin_ctz(m[2]);
-        m[2] &= m[2] - 1u;
-        return 64 + b;
-    }
-    if (m[3]) {
-        const int b = __builtin_ctz(m[3]);
-        m[3] &= m[3] - 1u;
-        return 96 + b;
-    }
-    return -1;
+    const uint32_t m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+    const bool z0 = m0 == 0u, z01 = z0 && m1 == 0u, z012 = z01 && m2 == 0u;
+    const uint32_t w = z0 ? (z01 ? (z012 ? m3 : m2) : m1) : m0;
+    const int base = z0 ? (z01 ? (z012 ? 96 : 64) : 32) : 0;
+    // clearing the lowest bit of an empty word leaves it empty, so each word
+    // may take it unless an earlier word holds the bit
+    m[0] = take ? m0 & (m0 - 1u) : m0;
+    m[1] = take && z0 ? m1 & (m1 - 1u) : m1;
+    m[2] = take && z01 ? m2 & (m2 - 1u) : m2;
+    m[3] = take && z012 ? m3 & (m3 - 1u) : m3;
+    return w != 0u ? base + __builtin_ctz(w) : -1;
 }
 
 // One exceptional bond (k) of the node whose values are given: closed-form
@@ -705,7 +698,8 @@ __device__ __forceinline__ ExcFetch<T> exc_fetch(const StepParams<T> &a, const S
     const int64_t off = (int64_t)f.x + (int64_t)f.y * a.PX + (int64_t)f.z * a.PXY;
     f.uj = src.get(f.x, f.y, f.z);
     f.s0j = ld(S0, off, lb1);
-    f.gj = ld(Gp, off * gstep, lb1 * (uint32_t)gstep);
+    f.gj = T(1);   // without a fracture-energy field its one word holds 1
+    if (gstep != 0) f.gj = ld(Gp, off * gstep, lb1 * (uint32_t)gstep);
     f.cj = T(1);
     if constexpr (CW) f.cj = fabs(f.uj.w);
     else if constexpr (HAS_C) f.cj = src.getc(f.x, f.y, f.z);
@@ -785,11 +779,11 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
             const uint64_t m = __ballot(cnt > r);
             const uint32_t n = (uint32_t)__popcll(m);
             if (n == 0 || fill + n > kList) break;
-            if (cnt > r) {
-                const int k = pop_slot(rem);
-                const uint32_t at = fill + (uint32_t)__popcll(m & below);
-                list[at] = (uint16_t)(lane << 8 | (mask_bit(dm, k) ? 128u : 0u) | (uint32_t)k);
-            }
+            const bool in = cnt > r;
+            const int k = pop_slot(rem, in);
+            const uint32_t at = fill + (uint32_t)__popcll(m & below);
+            const uint32_t entry = lane << 8 | (mask_bit(dm, k) ? 128u : 0u) | (uint32_t)k;
+            if (in) list[at] = (uint16_t)entry;
             fill += n;
             ++r;
         }
@@ -811,7 +805,11 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
         u1.w = T(1);
         const T s00 = shfl_t(s0i, o0), s01 = shfl_t(s0i, o1);
         const T c00 = HAS_C ? shfl_t(ci, o0) : T(1), c01 = HAS_C ? shfl_t(ci, o1) : T(1);
-        const T g00 = shfl_t(gi, o0), g01 = shfl_t(gi, o1);
+        T g00 = T(1), g01 = T(1);   // gi is 1 on every lane without a fracture-energy field
+        if (gstep != 0) {
+            g00 = shfl_t(gi, o0);
+            g01 = shfl_t(gi, o1);
+        }
         const uint32_t p0 = shfl_u32(p, o0), p1 = shfl_u32(p, o1);
         const uint32_t n0 = shfl_u32(node, o0), n1 = shfl_u32(node, o1);
         const uint32_t k0 = shfl_u32(key, o0), k1 = shfl_u32(key, o1);
@@ -836,19 +834,21 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
         uint32_t base = 0;
         for (uint32_t rr = r0; rr < r; ++rr) {
             const uint64_t m = __ballot(cnt > rr);
+            const uint32_t n = (uint32_t)__popcll(m);
             const bool mi = cnt > rr;
             const uint32_t idx = mi ? base + (uint32_t)__popcll(m & below) : lane;
+            // the round's results sit at list positions base .. base + n - 1
+            // (n <= 64), so of the two a lane holds at most one is wanted:
+            // entry lane + 64 when it lies in that range, else entry lane
+            const bool up = lane + 64u >= base && lane + 64u < base + n;
+            const T sx = up ? fx1 : fx0, sy = up ? fy1 : fy0, sz = up ? fz1 : fz0;
             const uint32_t srcl = idx & 63u;
-            const bool hi = idx >= 64u;
-            const T ax = shfl_t(fx0, srcl), ay = shfl_t(fy0, srcl), az = shfl_t(fz0, srcl);
-            const T bx = shfl_t(fx1, srcl), by = shfl_t(fy1, srcl), bz = shfl_t(fz1, srcl);
-            const uint32_t fl = shfl_u32(flags, srcl) >> (hi ? 2 : 0);
-            if (mi) {
-                const int k = pop_slot(walk);
-                if (fl & 1u) acc.add(hi ? bx : ax, hi ? by : ay, hi ? bz : az);
-                if (fl & 2u) set_mask_bit(dm, k);
-            }
-            base += (uint32_t)__popcll(m);
+            const T ax = shfl_t(sx, srcl), ay = shfl_t(sy, srcl), az = shfl_t(sz, srcl);
+            const uint32_t fl = shfl_u32(up ? flags >> 2 : flags, srcl);
+            const int k = pop_slot(walk, mi);
+            set_mask_bit(dm, k, mi && (fl & 2u));
+            if (mi && (fl & 1u)) acc.add(ax, ay, az);
+            base += n;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
