@@ -165,6 +165,22 @@ struct Acc3 {
             z += pz;
         }
     }
+    __device__ __forceinline__ void add_if(bool on, T px, T py, T pz)
+    {
+        if constexpr (KAHAN) {
+            T x1 = x, cx1 = cx, y1 = y, cy1 = cy, z1 = z, cz1 = cz;
+            kahan(x1, cx1, px);
+            kahan(y1, cy1, py);
+            kahan(z1, cz1, pz);
+            x = on ? x1 : x; cx = on ? cx1 : cx;
+            y = on ? y1 : y; cy = on ? cy1 : cy;
+            z = on ? z1 : z; cz = on ? cz1 : cz;
+        } else {
+            x = on ? x + px : x;
+            y = on ? y + py : y;
+            z = on ? z + pz : z;
+        }
+    }
     __device__ __forceinline__ static void kahan(T &s, T &c, T v)
     {
         T yv = v - c;
@@ -773,7 +789,6 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
     while (__any(cnt > r)) {
         // list rounds r0 .. r - 1 (at least one: a round has at most 64 bonds)
         const uint32_t r0 = r;
-        uint32_t walk[4] = {rem[0], rem[1], rem[2], rem[3]};
         uint32_t fill = 0;
         for (;;) {
             const uint64_t m = __ballot(cnt > r);
@@ -829,7 +844,10 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
         if (has1)
             live1 = exc_finish<T, HAS_C>(a, tab, Hs, lh1, u1, s01, c01, g01, (int)(ent1 & 127u), f1, now1, fx1, fy1,
                                          fz1);
-        const uint32_t flags = (live0 ? 1u : 0u) | (now0 ? 2u : 0u) | (live1 ? 4u : 0u) | (now1 ? 8u : 0u);
+        // per listed bond: live, now and its slot (9 bits; the second bond's
+        // from bit 16)
+        const uint32_t flags = (live0 ? 1u : 0u) | (now0 ? 2u : 0u) | (ent0 & 127u) << 2 |
+                               ((live1 ? 1u : 0u) | (now1 ? 2u : 0u) | (ent1 & 127u) << 2) << 16;
         // owners add their results round by round
         uint32_t base = 0;
         for (uint32_t rr = r0; rr < r; ++rr) {
@@ -844,10 +862,9 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
             const T sx = up ? fx1 : fx0, sy = up ? fy1 : fy0, sz = up ? fz1 : fz0;
             const uint32_t srcl = idx & 63u;
             const T ax = shfl_t(sx, srcl), ay = shfl_t(sy, srcl), az = shfl_t(sz, srcl);
-            const uint32_t fl = shfl_u32(up ? flags >> 2 : flags, srcl);
-            const int k = pop_slot(walk, mi);
-            set_mask_bit(dm, k, mi && (fl & 2u));
-            if (mi && (fl & 1u)) acc.add(ax, ay, az);
+            const uint32_t fl = shfl_u32(up ? flags >> 16 : flags, srcl);
+            set_mask_bit(dm, (int)((fl >> 2) & 127u), mi && (fl & 2u));
+            acc.add_if(mi && (fl & 1u), ax, ay, az);
             base += n;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
