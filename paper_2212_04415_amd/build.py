@@ -57,6 +57,28 @@ def kernel_resources(remarks: str):
     return out
 
 
+def resource_problems(res):
+    """Step-kernel resource use that fails the build, from kernel_resources()
+    output: FP32 step kernels that use scratch memory (spilled registers, or
+    a private array not kept in registers; a scratch access in the exception
+    pass's round loops costs a sixth of the cracking-load throughput), and
+    FP32 kernels of the default 16x4x4 brick without a micromodulus tile that
+    need more than 128 VGPRs (they hold 4 waves per SIMD only up to 128, the
+    38.4 KB tile allowing no more; with the c tile, LDS caps them at 3
+    anyway)."""
+    import re
+    out = []
+    scratch = [k for k, v in res.items() if "step_kernelIf" in k and
+               (v.get("VGPRSpill", 0) > 0 or v.get("ScratchSize", 0) > 0)]
+    if scratch:
+        out.append("FP32 step kernels use scratch memory: " + ", ".join(scratch))
+    wide = [f"{k} ({v.get('VGPRs')} VGPRs)" for k, v in res.items()
+            if re.search(r"step_kernelIfLb[01]ELb0ELb1ENS_5BrickILi16ELi4ELi4ELi2E", k) and v.get("VGPRs", 0) > 128]
+    if wide:
+        out.append("FP32 16x4x4 step kernels need more than 128 VGPRs: " + ", ".join(wide))
+    return out
+
+
 def _compile(cmd):
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
     if r.returncode != 0:
@@ -67,10 +89,8 @@ def _compile(cmd):
 
 def build(verbose: bool = False) -> str:
     """Compiles every source to an object in parallel, then links.  The step
-    kernels' register use is read from the compiler's resource remarks: an
-    FP32 step kernel that spills registers fails the build (it would run
-    several times slower), and so does an FP32 kernel of the default brick
-    that needs more than 128 VGPRs (it would lose a wave per SIMD)."""
+    kernels' resource use is read from the compiler's remarks, and what
+    resource_problems() names fails the build."""
     from concurrent.futures import ThreadPoolExecutor
     import tempfile
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -89,22 +109,12 @@ def build(verbose: bool = False) -> str:
         with ThreadPoolExecutor(max_workers=min(len(cmds), 16, max(1, os.cpu_count() or 1))) as ex:
             remarks = "".join(f.result() for f in [ex.submit(_compile, c) for c in cmds])
         res = {k: v for k, v in kernel_resources(remarks).items() if "step_kernel" in k}
-        spilled = [k for k, v in res.items() if "step_kernelIf" in k and v.get("VGPRSpill", 0) > 0]
         if verbose:
             for k, v in sorted(res.items()):
                 print(f"{k}: {v}", flush=True)
-        if spilled:
-            raise RuntimeError("FP32 step kernels spill registers: " + ", ".join(spilled))
-        # the default brick's FP32 kernels without a micromodulus tile hold 4
-        # waves per SIMD only up to 128 VGPRs (the 38.4 KB tile allows no
-        # more); a source change that pushes them past it costs a quarter of
-        # the throughput.  (With the c tile, LDS caps them at 3 anyway.)
-        import re
-        wide = [f"{k} ({v.get('VGPRs')} VGPRs)" for k, v in res.items()
-                if re.search(r"step_kernelIfLb[01]ELb0ELb1ENS_5BrickILi16ELi4ELi4ELi2E", k) and
-                v.get("VGPRs", 0) > 128]
-        if wide:
-            raise RuntimeError("FP32 16x4x4 step kernels need more than 128 VGPRs: " + ", ".join(wide))
+        problems = resource_problems(res)
+        if problems:
+            raise RuntimeError("; ".join(problems))
         tmp = LIB + ".tmp"
         link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
         if verbose:

@@ -227,3 +227,29 @@ def test_binding_constants_match_the_header():
     assert len(consts) >= 29
     for name, value in consts.items():
         assert getattr(pd, name) == value, name
+
+
+def test_build_rejects_scratch_and_wide_step_kernels():
+    """The build reads the compiler's resource remarks: an FP32 step kernel
+    with scratch memory (spills, or a private array) or a default-brick FP32
+    kernel past 128 VGPRs is named; FP64 kernels and the c-tile kernels
+    above 128 VGPRs are not."""
+    from paper_2212_04415_amd import build as BD
+    fast = "_ZN4pdmi11step_kernelIfLb1ELb0ELb1ENS_5BrickILi16ELi4ELi4ELi2EEEEEvNS_10StepParamsIT_EE"
+    ctile = "_ZN4pdmi11step_kernelIfLb1ELb1ELb1ENS_5BrickILi16ELi4ELi4ELi2EEEEEvNS_10StepParamsIT_EE"
+    f64 = "_ZN4pdmi11step_kernelIdLb0ELb0ELb1ENS_5BrickILi16ELi4ELi4ELi2EEEEEvNS_10StepParamsIT_EE"
+
+    def remarks(name, vgprs, scratch, spill):
+        pre = "step_kernels.h:1:1: remark: "
+        return (f"{pre}Function Name: {name} [-Rpass-analysis=kernel-resource-usage]\n"
+                f"{pre}    VGPRs: {vgprs} [-Rpass-analysis=kernel-resource-usage]\n"
+                f"{pre}    ScratchSize [bytes/lane]: {scratch} [-Rpass-analysis=kernel-resource-usage]\n"
+                f"{pre}    VGPRs Spill: {spill} [-Rpass-analysis=kernel-resource-usage]\n")
+
+    ok = BD.kernel_resources(remarks(fast, 121, 0, 0) + remarks(ctile, 140, 0, 0) + remarks(f64, 200, 64, 10))
+    assert ok[fast] == {"VGPRs": 121, "ScratchSize": 0, "VGPRSpill": 0}
+    assert BD.resource_problems(ok) == []
+    for vgprs, scratch, spill, what in ((121, 32, 0, "scratch"), (121, 16, 4, "scratch"), (129, 0, 0, "128 VGPRs")):
+        bad = BD.kernel_resources(remarks(fast, vgprs, scratch, spill))
+        (msg,) = BD.resource_problems(bad)
+        assert what in msg and fast in msg
