@@ -844,10 +844,12 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
         if (has1)
             live1 = exc_finish<T, HAS_C>(a, tab, Hs, lh1, u1, s01, c01, g01, (int)(ent1 & 127u), f1, now1, fx1, fy1,
                                          fz1);
-        // per listed bond: live, now and its slot (9 bits; the second bond's
-        // from bit 16)
-        const uint32_t flags = (live0 ? 1u : 0u) | (now0 ? 2u : 0u) | (ent0 & 127u) << 2 |
-                               ((live1 ? 1u : 0u) | (now1 ? 2u : 0u) | (ent1 & 127u) << 2) << 16;
+        // per listed bond: live, first damage (its bit joins the node's
+        // damage mask; a bond already in the mask only grows its history) and
+        // its slot (9 bits; the second bond's from bit 16)
+        const bool new0 = now0 && (ent0 & 128u) == 0u, new1 = now1 && (ent1 & 128u) == 0u;
+        const uint32_t flags = (live0 ? 1u : 0u) | (new0 ? 2u : 0u) | (ent0 & 127u) << 2 |
+                               ((live1 ? 1u : 0u) | (new1 ? 2u : 0u) | (ent1 & 127u) << 2) << 16;
         // owners add their results round by round
         uint32_t base = 0;
         for (uint32_t rr = r0; rr < r; ++rr) {
@@ -863,7 +865,7 @@ __device__ __forceinline__ void exc_pool(const StepParams<T> &a, const Src &src,
             const uint32_t srcl = idx & 63u;
             const T ax = shfl_t(sx, srcl), ay = shfl_t(sy, srcl), az = shfl_t(sz, srcl);
             const uint32_t fl = shfl_u32(up ? flags >> 16 : flags, srcl);
-            set_mask_bit(dm, (int)((fl >> 2) & 127u), mi && (fl & 2u));
+            if (mi && (fl & 2u)) set_mask_bit(dm, (int)((fl >> 2) & 127u), true);   // rare: a branch
             acc.add_if(mi && (fl & 1u), ax, ay, az);
             base += n;
         }
