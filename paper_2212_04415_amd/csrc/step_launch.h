@@ -11,6 +11,19 @@
 
 namespace pdmi {
 
+// A block copies the stencil's slot table into LDS one entry per thread, so
+// every launch shape below needs at least kStencil threads per block; with
+// fewer, the exception pass would decode unset entries into offsets outside
+// the padded grid.
+template <typename... BR>
+constexpr bool blocks_fill_slot_table()
+{
+    return ((BR::N >= kStencil) && ...);
+}
+static_assert(blocks_fill_slot_table<Brick<16, 4, 4, 2>, Brick<8, 8, 4>, Brick<12, 4, 4>, Brick<256, 1, 1>,
+                                     PlaneBrick<64, 4>, PlaneBrick<32, 8>, PlaneBrick<32, 4>, PlaneBrick<256, 1>>(),
+              "a launch shape's block is smaller than the slot table it fills");
+
 #ifdef PD_STEP_LAUNCH_IMPL
 template <typename T, bool KAHAN, bool HAS_C>
 static void launch_shape(int shape, bool plane, dim3 grid, hipStream_t st, const StepParams<T> &a)
